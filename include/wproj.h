@@ -1,0 +1,199 @@
+/*
+ * wproj.h -- C ABI of the MI355X (gfx950) w-projection imaging library.
+ *
+ * W-projection wide-field imaging (the method whose parallel implementation
+ * Lao et al. 2019 study; they cite Cornwell, Golap & Bhatnagar 2008 for the
+ * mathematics, Sections 1-2): each visibility is convolved onto one uv-grid
+ * with an oversampled, w-dependent kernel (a prolate spheroidal taper times
+ * the w phase screen, Fourier transformed), the grid is inverse-FFT'd and the
+ * taper is divided out of the image.  Degridding is the adjoint.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers are DEVICE pointers owned by the caller unless marked (host).
+ *     Nothing returned by the library aliases caller memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls only enqueue
+ *     work on it and return; nothing synchronises except wproj_make_kernels.
+ *   - Every entry point returns a wproj_status; on a non-OK status
+ *     wproj_last_error() gives a message for the calling thread and no work
+ *     has been enqueued.  No C++ exception crosses the ABI.
+ *   - Grids are [n_images][n][n] complex, row-major [y][x], interleaved
+ *     (re, im): complex128 for WPROJ_F64, complex64 otherwise.  Images are
+ *     [n_images][n][n] real (float64 for WPROJ_F64, float32 otherwise).
+ *     Cell X of a grid holds u = (X - n/2)/FoV, pixel x holds
+ *     l = (x - n/2) cell_rad, FoV = n cell_rad.
+ *   - uvw is always float64 [nvis][3], in wavelengths.
+ *   - Per visibility: weight 0 = flagged (skipped); a negative or non-finite
+ *     weight is skipped and counted; non-finite uvw or a kernel footprint
+ *     that leaves the grid drops the visibility (counted); with more than one
+ *     w-plane, |w| > w_max is clamped to the edge plane (counted).
+ *   - A handle is immutable after wproj_make_kernels and may be used from
+ *     several streams at once; the caller's workspace must not be shared by
+ *     calls that run concurrently.
+ */
+#ifndef WPROJ_H
+#define WPROJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WPROJ_F64 = 0,          /* FP64 tables, FP64 visibilities, FP64 grid */
+  WPROJ_F32 = 1,          /* FP32 tables, FP32 visibilities/weights, FP32 grid */
+  WPROJ_F32_F16TABLE = 2  /* as WPROJ_F32 but kernel tables stored in FP16 */
+} wproj_precision;
+
+typedef enum {
+  WPROJ_ALGO_TILED = 0, /* device binning by (image, uv-tile, w-plane) + LDS-tile gridder */
+  WPROJ_ALGO_PLAIN = 1  /* one pass, global atomics per tap, no binning (comparison path) */
+} wproj_algorithm;
+
+typedef enum {
+  WPROJ_OK = 0,
+  WPROJ_EINVAL = -1,       /* invalid argument or parameter block */
+  WPROJ_ENOMEM = -2,       /* device allocation failed (wproj_make_kernels only) */
+  WPROJ_EHIP = -3,         /* a HIP runtime call failed */
+  WPROJ_EUNSUPPORTED = -4, /* valid but not supported by this build (message says why) */
+  WPROJ_EWORKSPACE = -5,   /* workspace smaller than wproj_workspace_size() */
+  WPROJ_EFFT = -6          /* rocFFT plan creation or execution failed */
+} wproj_status;
+
+/*
+ * Parameter block.  The paper's "primary argument settings" are the image
+ * size, cell size, number of w-planes and full support of the convolution
+ * kernel (Section 3.1); precision is its single/double comparison
+ * (Sections 3.2, 4).  Oversampling, the w range and the kernel-generation
+ * sample count are the standard w-projection parameters the paper leaves
+ * implicit.
+ */
+typedef struct {
+  int32_t n;                /* grid/image side N: even, 2..32768 */
+  int32_t n_wplanes;        /* N_w >= 1: planes at w_p = -w_max + p 2 w_max/(N_w-1); one plane = w 0 */
+  double cell_rad;          /* image cell (radians) > 0, with n * cell_rad < 2 */
+  double w_max;             /* >= 0 (> 0 when N_w > 1), wavelengths */
+  int32_t support;          /* S: full support in cells of the w = 0 kernel, 1..32; also sets the
+                               taper bandwidth c = pi S / 2 */
+  int32_t oversample;       /* O: 1..256; S_p * O must be even */
+  const int32_t *support_per_plane; /* (host, nullable) [N_w] full supports S_p, 1..32;
+                               NULL = S for every plane.  Read during wproj_make_kernels only. */
+  int32_t kernel_image_size; /* m: image-domain samples per axis for kernel generation; even, 2..4096 */
+  int32_t precision;        /* wproj_precision */
+  int32_t n_images;         /* >= 1: independent images gridded in one call (e.g. channels) */
+  int32_t algorithm;        /* wproj_algorithm */
+  int32_t tile;             /* tiled gridder tile side: 0 = default, else 32, 64 or 128 */
+  int32_t reserved[5];      /* must be zero */
+} wproj_params;
+
+typedef struct wproj_kernels wproj_kernels; /* opaque handle */
+
+/*
+ * Build the oversampled w-kernel tables on the device, in FP64, then store
+ * them in the handle's precision.  For plane p with support S_p:
+ *   screen  s_p(l, m) = psi(l/l_max) psi(m/l_max) exp(+2 pi i w_p (sqrt(1-l^2-m^2) - 1)),
+ *           sampled at the m x m cell-centred points nu_i = (2i + 1 - m)/m, l = nu l_max;
+ *   table   C_p(a, b) = sum_{i,j} s_p(l_i, m_j) exp(-2 pi i (a l_i + b m_j)/(O FoV)),
+ *           its Fourier transform at uv offsets (a/O, b/O) cells, a, b in (-S_p O/2, S_p O/2];
+ *   layout  [ov][ou][kv][ku] with tap (kv, ku) of sub-kernel (ov, ou) = C_p(b0 + kv O, a0 + ku O),
+ *           a0 = ou + 1 - S_p O/2; each sub-kernel is divided by its complex tap sum.
+ * psi is the zeroth-order prolate spheroidal function with c = pi S/2, and
+ * the grid correction kappa(x) = 1/psi((x - n/2)/(n/2)) (0 on the edge pixel
+ * x = 0) is stored alongside.  Launches on `stream`, synchronises it, and
+ * returns the handle in *out (host pointer).  Errors: WPROJ_EINVAL for an
+ * invalid block, WPROJ_ENOMEM, WPROJ_EHIP, WPROJ_EFFT.
+ */
+int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels **out);
+
+/* Release a handle (NULL is accepted).  The caller must have finished all work using it. */
+int wproj_free_kernels(wproj_kernels *k);
+
+/* What wproj_export copies. */
+typedef enum {
+  WPROJ_EXPORT_TABLES = 0,      /* tables as stored: c128, c64 or (half re, half im) per tap */
+  WPROJ_EXPORT_TABLE_OFFSETS = 1, /* int64 [N_w + 1]: first tap of each plane */
+  WPROJ_EXPORT_KAPPA = 2,       /* float64 [n]: grid-correction factors kappa(x) */
+  WPROJ_EXPORT_TAPER = 3,       /* float64 [m]: psi(nu_i) at the kernel-generation samples */
+  WPROJ_EXPORT_SUPPORTS = 4     /* int32 [N_w]: S_p */
+} wproj_export_what;
+
+/*
+ * Copy a table held by the handle into device memory dst (bytes available
+ * in dst_bytes), enqueued on stream.  With dst == NULL only *needed (host) is
+ * written.  Errors: WPROJ_EINVAL (unknown `what`, dst_bytes too small).
+ */
+int wproj_export(const wproj_kernels *k, int what, void *dst, int64_t dst_bytes, int64_t *needed,
+                 void *stream);
+
+/*
+ * Bytes of device workspace the grid/degrid/image calls need for nvis
+ * visibilities (>= 0), or a negative wproj_status.  The workspace is scratch:
+ * its contents on entry are ignored and on return undefined.
+ */
+int64_t wproj_workspace_size(const wproj_kernels *k, int64_t nvis);
+
+/*
+ * Gridding (convolutional resampling onto the uv-grid; the "gridding" step
+ * the paper parallelises, Section 2):
+ *   grid[i][y0+kv][x0+ku] += W_j V_j T_p[ov][ou][kv][ku]   for every valid visibility j of image i,
+ *   weight_sum[i] += W_j                                   over the same visibilities,
+ * with p the nearest w-plane (ties round up) and, per axis, g = u FoV + n/2,
+ * q = floor(g O + 1/2), x0 = floor((q - S_p O/2)/O) + 1, ou = x0 O - q + S_p O/2 - 1.
+ *   uvw           float64 [nvis][3]
+ *   vis           [nvis] complex128 (WPROJ_F64) or complex64
+ *   weight        [nvis] float64 (WPROJ_F64) or float32
+ *   image_offsets int64 [n_images + 1], ascending; rows [off[i], off[i+1]) belong to
+ *                 image i, rows outside [off[0], off[n_images]) are ignored.  May be
+ *                 NULL when n_images == 1 (all rows belong to image 0).
+ *   grid          accumulated into (the caller zeroes it first)
+ *   weight_sum    float64 [n_images], accumulated into (nullable)
+ *   counters      int64 [3], accumulated into (nullable): dropped (non-finite uvw or
+ *                 off-grid), w clamped, bad weight
+ * Errors: WPROJ_EINVAL (NULL required pointer, nvis < 0), WPROJ_EWORKSPACE.
+ */
+int wproj_grid(const wproj_kernels *k, int64_t nvis, const double *uvw, const void *vis,
+               const void *weight, const int64_t *image_offsets, void *grid, double *weight_sum,
+               int64_t *counters, void *workspace, int64_t workspace_bytes, void *stream);
+
+/*
+ * Degridding, the adjoint of gridding (prediction of model visibilities):
+ *   vis_out[j] = sum_{kv,ku} conj(T_p[ov][ou][kv][ku]) model_grid[i][y0+kv][x0+ku]
+ * with the same footprint rule; rows with non-finite uvw or off-grid footprints, and
+ * rows outside every image range, are set to 0.  vis_out is overwritten
+ * ([nvis] complex128 for WPROJ_F64, else complex64).  No weights are applied.
+ * Errors: WPROJ_EINVAL, WPROJ_EWORKSPACE.
+ */
+int wproj_degrid(const wproj_kernels *k, int64_t nvis, const double *uvw, const void *model_grid,
+                 const int64_t *image_offsets, void *vis_out, void *workspace,
+                 int64_t workspace_bytes, void *stream);
+
+typedef enum {
+  WPROJ_GRID_TO_IMAGE = 0,     /* image = Re(IDFT(grid)) kappa(x) kappa(y) / weight_sum */
+  WPROJ_IMAGE_TO_GRID = 1,     /* grid  = DFT(kappa(x) kappa(y) image) (model prediction) */
+  WPROJ_GRID_TO_IMAGE_RAW = 2  /* image = Re(IDFT(grid)) kappa(x) kappa(y) (no weight_sum) */
+} wproj_direction;
+
+/*
+ * Transforms between grid and image; the DFTs are centred and unnormalised:
+ *   IDFT(G)[y][x] = sum_{Y,X} G[Y][X] exp(+2 pi i ((X - n/2)(x - n/2) + (Y - n/2)(y - n/2))/n)
+ *   DFT(I)[Y][X]  = sum_{y,x} I[y][x] exp(-2 pi i ((X - n/2)(x - n/2) + (Y - n/2)(y - n/2))/n)
+ * (the paper's final IFFT, Sections 2.1-2.2; rocFFT does the 2D transforms).
+ * GRID_TO_IMAGE*: grid is transformed IN PLACE (its contents are destroyed) and
+ * image is written.  IMAGE_TO_GRID: image is read and grid is overwritten.
+ * weight_sum (float64 [n_images], device) is read only by GRID_TO_IMAGE.
+ * Errors: WPROJ_EINVAL, WPROJ_EWORKSPACE, WPROJ_EFFT.
+ */
+int wproj_image(const wproj_kernels *k, int direction, void *grid, void *image,
+                const double *weight_sum, void *workspace, int64_t workspace_bytes, void *stream);
+
+/* Message describing the last non-OK status returned on the calling thread ("" if none). */
+const char *wproj_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int wproj_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WPROJ_H */

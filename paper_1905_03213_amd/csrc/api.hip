@@ -1,0 +1,499 @@
+// C ABI entry points: argument checking, handle construction (kernel tables, grid
+// correction, rocFFT plans) and dispatch to the kernel launchers.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+
+#include "wproj_tiled.h"
+
+using namespace wproj;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(WPROJ_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Prolate spheroidal psi_0 as a Legendre series (host, FP64).
+//
+// psi_0(c, x) is the eigenfunction with the smallest eigenvalue of
+// -d/dx[(1 - x^2) d/dx] + c^2 x^2.  In the normalised Legendre basis
+// Pbar_n = sqrt(n + 1/2) P_n the even part is the symmetric tridiagonal matrix
+//   d_k = n(n+1) + c^2 (2n(n+1) - 1)/((2n+3)(2n-1)),
+//   e_k = c^2 (n+1)(n+2)/((2n+3) sqrt((2n+1)(2n+5))),      n = 2k,
+// (Xiao, Rokhlin & Yarvin 2001).  The smallest eigenvalue is found by Sturm-count
+// bisection, its eigenvector by inverse iteration with a shift just below it (the
+// shifted matrix is then positive definite, so the tridiagonal solve needs no
+// pivoting).  Returned: coefficients of P_0, P_2, ... with psi_0(0) > 0.
+// ---------------------------------------------------------------------------
+std::vector<double> prolate_legendre(double c) {
+  const int K = (int)c + 40;
+  std::vector<double> d(K), e(K > 1 ? K - 1 : 1, 0.0);
+  for (int k = 0; k < K; ++k) {
+    const double n = 2.0 * k;
+    d[k] = n * (n + 1.0) + c * c * (2.0 * n * (n + 1.0) - 1.0) / ((2.0 * n + 3.0) * (2.0 * n - 1.0));
+    if (k + 1 < K)
+      e[k] = c * c * (n + 1.0) * (n + 2.0) / ((2.0 * n + 3.0) * sqrt((2.0 * n + 1.0) * (2.0 * n + 5.0)));
+  }
+  auto below = [&](double x) {  // number of eigenvalues < x
+    int cnt = 0;
+    double q = d[0] - x;
+    if (q < 0) ++cnt;
+    for (int k = 1; k < K; ++k) {
+      if (q == 0.0) q = 1e-300;
+      q = d[k] - x - e[k - 1] * e[k - 1] / q;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  double lo = d[0], hi = d[0];
+  for (int k = 0; k < K; ++k) {
+    double r = (k > 0 ? fabs(e[k - 1]) : 0.0) + (k + 1 < K ? fabs(e[k]) : 0.0);
+    lo = std::min(lo, d[k] - r);
+    hi = std::max(hi, d[k] + r);
+  }
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (below(mid) >= 1)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  const double chi = 0.5 * (lo + hi);
+  const double sigma = chi - 1e-9 * std::max(1.0, fabs(chi));
+  std::vector<double> x(K, 1.0), y(K), cp(K), dp(K);
+  for (int iter = 0; iter < 4; ++iter) {
+    // Thomas algorithm on (A - sigma I) y = x
+    double b0 = d[0] - sigma;
+    cp[0] = (K > 1 ? e[0] : 0.0) / b0;
+    dp[0] = x[0] / b0;
+    for (int k = 1; k < K; ++k) {
+      double den = (d[k] - sigma) - e[k - 1] * cp[k - 1];
+      cp[k] = (k + 1 < K ? e[k] : 0.0) / den;
+      dp[k] = (x[k] - e[k - 1] * dp[k - 1]) / den;
+    }
+    y[K - 1] = dp[K - 1];
+    for (int k = K - 2; k >= 0; --k) y[k] = dp[k] - cp[k] * y[k + 1];
+    double nrm = 0.0;
+    for (int k = 0; k < K; ++k) nrm += y[k] * y[k];
+    nrm = sqrt(nrm);
+    for (int k = 0; k < K; ++k) x[k] = y[k] / nrm;
+  }
+  std::vector<double> coef(K);
+  double at0 = 0.0, p2k0 = 1.0;  // P_{2k}(0) = (-1)^k (2k-1)!!/(2k)!!
+  for (int k = 0; k < K; ++k) {
+    coef[k] = x[k] * sqrt(2.0 * k + 0.5);
+    at0 += coef[k] * p2k0;
+    p2k0 *= -(2.0 * k + 1.0) / (2.0 * k + 2.0);
+  }
+  if (at0 < 0)
+    for (double &v : coef) v = -v;
+  return coef;
+}
+
+int validate(const wproj_params *p, std::vector<int32_t> &supp) {
+  if (!p) return fail(WPROJ_EINVAL, "params is NULL");
+  const int n = p->n;
+  if (n < 2 || n > 32768 || (n & 1)) return fail(WPROJ_EINVAL, "n must be even in [2, 32768]");
+  if (!(isfinite(p->cell_rad) && p->cell_rad > 0.0 && (double)n * p->cell_rad < 2.0))
+    return fail(WPROJ_EINVAL, "cell_rad must be > 0 with n * cell_rad < 2");
+  if (p->n_wplanes < 1 || p->n_wplanes > 4096)
+    return fail(WPROJ_EINVAL, "n_wplanes must be in [1, 4096]");
+  if (!(isfinite(p->w_max) && p->w_max >= 0.0)) return fail(WPROJ_EINVAL, "w_max must be >= 0");
+  if (p->n_wplanes > 1 && !(p->w_max > 0.0))
+    return fail(WPROJ_EINVAL, "w_max must be > 0 with more than one w-plane");
+  if (p->support < 1 || p->support > 32) return fail(WPROJ_EINVAL, "support must be in [1, 32]");
+  if (p->oversample < 1 || p->oversample > 256)
+    return fail(WPROJ_EINVAL, "oversample must be in [1, 256]");
+  if (p->kernel_image_size < 2 || p->kernel_image_size > 4096 || (p->kernel_image_size & 1))
+    return fail(WPROJ_EINVAL, "kernel_image_size must be even in [2, 4096]");
+  if (p->precision < WPROJ_F64 || p->precision > WPROJ_F32_F16TABLE)
+    return fail(WPROJ_EINVAL, "unknown precision %d", p->precision);
+  if (p->n_images < 1) return fail(WPROJ_EINVAL, "n_images must be >= 1");
+  if (p->algorithm != WPROJ_ALGO_TILED && p->algorithm != WPROJ_ALGO_PLAIN)
+    return fail(WPROJ_EINVAL, "unknown algorithm %d", p->algorithm);
+  if (p->tile != 0 && p->tile != 32 && p->tile != 64 && p->tile != 128)
+    return fail(WPROJ_EINVAL, "tile must be 0, 32, 64 or 128");
+  for (int r : p->reserved)
+    if (r != 0) return fail(WPROJ_EINVAL, "reserved fields must be zero");
+  supp.assign(p->n_wplanes, p->support);
+  if (p->support_per_plane)
+    for (int i = 0; i < p->n_wplanes; ++i) supp[i] = p->support_per_plane[i];
+  for (int s : supp) {
+    if (s < 1 || s > 32 || s > n) return fail(WPROJ_EINVAL, "plane support must be in [1, min(32, n)]");
+    if (((int64_t)s * p->oversample) & 1) return fail(WPROJ_EINVAL, "S_p * oversample must be even");
+  }
+  return WPROJ_OK;
+}
+
+void destroy(wproj_kernels *k) {
+  if (!k) return;
+  if (k->fft_fwd) rocfft_plan_destroy(k->fft_fwd);
+  if (k->fft_inv) rocfft_plan_destroy(k->fft_inv);
+  (void)hipFree(k->d_supp);
+  (void)hipFree(k->d_tab_off);
+  (void)hipFree(k->d_tab);
+  (void)hipFree(k->d_kappa);
+  (void)hipFree(k->d_taper);
+  delete k;
+}
+
+std::once_flag g_fft_once;
+rocfft_status g_fft_setup = rocfft_status_success;
+
+struct TempBuffers {
+  void *p[4] = {nullptr, nullptr, nullptr, nullptr};
+  ~TempBuffers() {
+    for (void *q : p) (void)hipFree(q);
+  }
+};
+
+int check_device(const wproj_kernels *k) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(WPROJ_EHIP, "hipGetDevice failed");
+  if (dev != k->device)
+    return fail(WPROJ_EINVAL, "handle was built on device %d but device %d is current", k->device, dev);
+  return WPROJ_OK;
+}
+
+constexpr int64_t kAlign = 256;
+inline int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+BinShape bin_shape(const wproj_kernels *k) {
+  BinShape B;
+  B.tile = k->tile;
+  B.ntx = (k->params.n + k->tile - 1) / k->tile;
+  B.nty = B.ntx;
+  B.kw = k->plane_in_key ? k->params.n_wplanes : 1;
+  B.chunk = k->chunk;
+  B.n_tiles = (int64_t)k->params.n_images * B.ntx * B.nty;
+  B.n_keys = B.n_tiles * B.kw;
+  return B;
+}
+
+// Lays the binning buffers out from `base` (nullptr: sizes only); returns total bytes.
+int64_t carve(const wproj_kernels *k, int64_t nvis, char *base, BinWorkspace &W) {
+  const BinShape B = bin_shape(k);
+  const int64_t rec_bytes = k->params.precision == WPROJ_F64 ? sizeof(RecordF64) : sizeof(RecordF32);
+  const int64_t max_items = B.n_tiles + nvis / B.chunk + 1;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    char *p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  W.keys = (uint32_t *)take(4 * nvis);
+  W.slots = (uint32_t *)take(4 * nvis);
+  W.rec = take(rec_bytes * nvis);
+  W.count = (uint32_t *)take(4 * B.n_keys);
+  W.offset = (uint32_t *)take(4 * (B.n_keys + 1));
+  W.nch = (uint32_t *)take(4 * B.n_tiles);
+  W.choff = (uint32_t *)take(4 * (B.n_tiles + 1));
+  W.items = (WorkItem *)take((int64_t)sizeof(WorkItem) * max_items);
+  W.scan_tmp = (uint32_t *)take(4 * scan_temp_words(std::max(B.n_keys, B.n_tiles)));
+  W.counter = (uint32_t *)take(4);
+  return off;
+}
+
+int64_t workspace_bytes_for(const wproj_kernels *k, int64_t nvis) {
+  int64_t ws = align_up((int64_t)k->fft_work_bytes);
+  if (k->params.algorithm == WPROJ_ALGO_TILED) {
+    BinWorkspace W;
+    ws = std::max(ws, carve(k, nvis, nullptr, W));
+  }
+  return ws;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *wproj_last_error(void) { return g_err.c_str(); }
+
+int wproj_version(void) { return 100; }
+
+int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels **out) {
+  g_err.clear();
+  if (!out) return fail(WPROJ_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::vector<int32_t> supp;
+  int rc = validate(params, supp);
+  if (rc != WPROJ_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+
+  wproj_kernels *k = new (std::nothrow) wproj_kernels();
+  if (!k) return fail(WPROJ_ENOMEM, "host allocation failed");
+  struct Guard {
+    wproj_kernels *k;
+    ~Guard() { destroy(k); }
+  } guard{k};
+
+  k->params = *params;
+  k->params.support_per_plane = nullptr;
+  if (hipGetDevice(&k->device) != hipSuccess) return fail(WPROJ_EHIP, "hipGetDevice failed");
+  const int n = params->n, n_w = params->n_wplanes, O = params->oversample;
+  const int m = params->kernel_image_size;
+  k->supp_host = supp;
+  k->s_max = *std::max_element(supp.begin(), supp.end());
+  k->uniform_support = std::all_of(supp.begin(), supp.end(), [&](int v) { return v == supp[0]; });
+  k->tab_off_host.assign(n_w + 1, 0);
+  for (int p = 0; p < n_w; ++p)
+    k->tab_off_host[p + 1] = k->tab_off_host[p] + (int64_t)O * O * supp[p] * supp[p];
+  k->n_taps = k->tab_off_host[n_w];
+  k->tap_bytes = params->precision == WPROJ_F64 ? 16 : params->precision == WPROJ_F32 ? 8 : 4;
+  {
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, k->device));
+    k->n_cu = prop.multiProcessorCount;
+    k->max_lds = prop.sharedMemPerBlock;
+  }
+  if (params->tile) {
+    k->tile = params->tile;
+    if (params->algorithm == WPROJ_ALGO_TILED && tile_shape(k, k->tile).lds_bytes + 256 > k->max_lds)
+      return fail(WPROJ_EUNSUPPORTED, "tile %d with support %d needs %zu bytes of LDS, %zu available",
+                  k->tile, k->s_max, tile_shape(k, k->tile).lds_bytes, k->max_lds);
+  } else {
+    k->tile = 64;
+    while (k->tile > 16 && tile_shape(k, k->tile).lds_bytes + 256 > k->max_lds) k->tile /= 2;
+  }
+  {
+    const int64_t nt = (params->n + k->tile - 1) / k->tile;
+    k->plane_in_key = (int64_t)params->n_images * nt * nt * params->n_wplanes <= (1ll << 24);
+  }
+
+  Geometry &G = k->geo;
+  G.n = n;
+  G.O = O;
+  G.n_w = n_w;
+  G.n_images = params->n_images;
+  G.fov = (double)n * params->cell_rad;
+  G.w_max = params->w_max;
+  G.dw = n_w > 1 ? (2.0 * params->w_max) / (double)(n_w - 1) : 0.0;
+
+  if (hipMalloc(&k->d_supp, sizeof(int32_t) * n_w) != hipSuccess ||
+      hipMalloc(&k->d_tab_off, sizeof(int64_t) * (n_w + 1)) != hipSuccess ||
+      hipMalloc(&k->d_tab, (size_t)k->n_taps * k->tap_bytes) != hipSuccess ||
+      hipMalloc(&k->d_kappa, sizeof(double) * n) != hipSuccess ||
+      hipMalloc(&k->d_taper, sizeof(double) * m) != hipSuccess)
+    return fail(WPROJ_ENOMEM, "device allocation of kernel tables (%lld taps) failed",
+                (long long)k->n_taps);
+  G.supp = k->d_supp;
+  G.tab_off = k->d_tab_off;
+  HIP_TRY(hipMemcpyAsync(k->d_supp, supp.data(), sizeof(int32_t) * n_w, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(k->d_tab_off, k->tab_off_host.data(), sizeof(int64_t) * (n_w + 1),
+                         hipMemcpyHostToDevice, s));
+
+  // taper and correction
+  std::vector<double> coef = prolate_legendre(M_PI * params->support / 2.0);
+  TempBuffers tmp;
+  HIP_TRY(hipMalloc(&tmp.p[0], sizeof(double) * coef.size()));
+  HIP_TRY(hipMemcpyAsync(tmp.p[0], coef.data(), sizeof(double) * coef.size(),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_taper((const double *)tmp.p[0], (int)coef.size(), m, n, k->d_taper, k->d_kappa, s));
+
+  // tables, a batch of planes at a time
+  const int so_max = k->s_max * O;
+  const int64_t per_plane = 16 * ((int64_t)m * m + (int64_t)m * so_max + (int64_t)so_max * so_max);
+  int batch = (int)std::max<int64_t>(1, std::min<int64_t>(n_w, (int64_t)(512ll << 20) / per_plane));
+  HIP_TRY(hipMalloc(&tmp.p[1], (size_t)batch * m * m * 16));
+  HIP_TRY(hipMalloc(&tmp.p[2], (size_t)batch * m * so_max * 16));
+  HIP_TRY(hipMalloc(&tmp.p[3], (size_t)batch * so_max * so_max * 16));
+  for (int p0 = 0; p0 < n_w; p0 += batch) {
+    const int np = std::min(batch, n_w - p0);
+    HIP_TRY(launch_screen(k->d_taper, m, G.fov, G.w_max, G.dw, n_w, p0, np, (double2 *)tmp.p[1], s));
+    HIP_TRY(launch_table_dft((const double2 *)tmp.p[1], m, O, k->d_supp, p0, np, so_max,
+                             (double2 *)tmp.p[2], (double2 *)tmp.p[3], s));
+    HIP_TRY(launch_normalise((const double2 *)tmp.p[3], so_max, O, k->d_supp, k->d_tab_off, p0, np,
+                             params->precision, k->d_tab, s));
+  }
+
+  // FFT plans (batched over images, in place, unnormalised)
+  std::call_once(g_fft_once, [] { g_fft_setup = rocfft_setup(); });
+  if (g_fft_setup != rocfft_status_success) return fail(WPROJ_EFFT, "rocfft_setup failed");
+  const size_t lengths[2] = {(size_t)n, (size_t)n};
+  const rocfft_precision fp =
+      params->precision == WPROJ_F64 ? rocfft_precision_double : rocfft_precision_single;
+  if (rocfft_plan_create(&k->fft_inv, rocfft_placement_inplace,
+                         rocfft_transform_type_complex_inverse, fp, 2, lengths,
+                         (size_t)params->n_images, nullptr) != rocfft_status_success ||
+      rocfft_plan_create(&k->fft_fwd, rocfft_placement_inplace,
+                         rocfft_transform_type_complex_forward, fp, 2, lengths,
+                         (size_t)params->n_images, nullptr) != rocfft_status_success)
+    return fail(WPROJ_EFFT, "rocfft_plan_create failed for %dx%d x %d", n, n, params->n_images);
+  size_t w1 = 0, w2 = 0;
+  rocfft_plan_get_work_buffer_size(k->fft_inv, &w1);
+  rocfft_plan_get_work_buffer_size(k->fft_fwd, &w2);
+  k->fft_work_bytes = std::max(w1, w2);
+
+  HIP_TRY(hipStreamSynchronize(s));
+  guard.k = nullptr;
+  *out = k;
+  return WPROJ_OK;
+}
+
+int wproj_free_kernels(wproj_kernels *k) {
+  g_err.clear();
+  destroy(k);
+  return WPROJ_OK;
+}
+
+int wproj_export(const wproj_kernels *k, int what, void *dst, int64_t dst_bytes, int64_t *needed,
+                 void *stream) {
+  g_err.clear();
+  if (!k) return fail(WPROJ_EINVAL, "handle is NULL");
+  const void *src = nullptr;
+  int64_t bytes = 0;
+  switch (what) {
+    case WPROJ_EXPORT_TABLES:
+      src = k->d_tab;
+      bytes = k->n_taps * (int64_t)k->tap_bytes;
+      break;
+    case WPROJ_EXPORT_TABLE_OFFSETS:
+      src = k->d_tab_off;
+      bytes = 8 * (int64_t)(k->params.n_wplanes + 1);
+      break;
+    case WPROJ_EXPORT_KAPPA:
+      src = k->d_kappa;
+      bytes = 8 * (int64_t)k->params.n;
+      break;
+    case WPROJ_EXPORT_TAPER:
+      src = k->d_taper;
+      bytes = 8 * (int64_t)k->params.kernel_image_size;
+      break;
+    case WPROJ_EXPORT_SUPPORTS:
+      src = k->d_supp;
+      bytes = 4 * (int64_t)k->params.n_wplanes;
+      break;
+    default:
+      return fail(WPROJ_EINVAL, "unknown export %d", what);
+  }
+  if (needed) *needed = bytes;
+  if (!dst) return WPROJ_OK;
+  if (dst_bytes < bytes) return fail(WPROJ_EINVAL, "dst holds %lld bytes, %lld needed",
+                                     (long long)dst_bytes, (long long)bytes);
+  HIP_TRY(hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return WPROJ_OK;
+}
+
+int64_t wproj_workspace_size(const wproj_kernels *k, int64_t nvis) {
+  g_err.clear();
+  if (!k) return fail(WPROJ_EINVAL, "handle is NULL");
+  if (nvis < 0) return fail(WPROJ_EINVAL, "nvis < 0");
+  return workspace_bytes_for(k, nvis);
+}
+
+int wproj_grid(const wproj_kernels *k, int64_t nvis, const double *uvw, const void *vis,
+               const void *weight, const int64_t *image_offsets, void *grid, double *weight_sum,
+               int64_t *counters, void *workspace, int64_t workspace_bytes, void *stream) {
+  g_err.clear();
+  if (!k) return fail(WPROJ_EINVAL, "handle is NULL");
+  if (nvis < 0) return fail(WPROJ_EINVAL, "nvis < 0");
+  if (!grid) return fail(WPROJ_EINVAL, "grid is NULL");
+  if (nvis > 0 && (!uvw || !vis || !weight)) return fail(WPROJ_EINVAL, "uvw, vis and weight are required");
+  if (k->params.n_images > 1 && !image_offsets)
+    return fail(WPROJ_EINVAL, "image_offsets is required when n_images > 1");
+  int rc = check_device(k);
+  if (rc != WPROJ_OK) return rc;
+  const int64_t need = workspace_bytes_for(k, nvis);
+  if (workspace_bytes < need || (need > 0 && !workspace))
+    return fail(WPROJ_EWORKSPACE, "workspace of %lld bytes given, %lld needed",
+                (long long)workspace_bytes, (long long)need);
+  if (nvis == 0) return WPROJ_OK;
+  hipStream_t s = (hipStream_t)stream;
+  if (k->params.algorithm == WPROJ_ALGO_PLAIN) {
+    HIP_TRY(launch_plain_grid(k, nvis, uvw, vis, weight, image_offsets, grid, weight_sum, counters, s));
+    return WPROJ_OK;
+  }
+  if (nvis > 0xfffffffell)
+    return fail(WPROJ_EINVAL, "the tiled gridder takes at most 2^32 - 2 visibilities per call");
+  if (k->n_taps > (int64_t)kTapMask)
+    return fail(WPROJ_EUNSUPPORTED, "kernel tables of %lld taps exceed the tiled gridder's 2^26",
+                (long long)k->n_taps);
+  const BinShape B = bin_shape(k);
+  BinWorkspace W;
+  carve(k, nvis, (char *)workspace, W);
+  HIP_TRY(launch_bin(k, B, nvis, uvw, vis, weight, image_offsets, weight_sum, counters, W, s));
+  HIP_TRY(launch_tiled_grid(k, B, W, grid, s));
+  return WPROJ_OK;
+}
+
+int wproj_degrid(const wproj_kernels *k, int64_t nvis, const double *uvw, const void *model_grid,
+                 const int64_t *image_offsets, void *vis_out, void *workspace,
+                 int64_t workspace_bytes, void *stream) {
+  g_err.clear();
+  if (!k) return fail(WPROJ_EINVAL, "handle is NULL");
+  if (nvis < 0) return fail(WPROJ_EINVAL, "nvis < 0");
+  if (nvis > 0 && (!uvw || !model_grid || !vis_out))
+    return fail(WPROJ_EINVAL, "uvw, model_grid and vis_out are required");
+  if (k->params.n_images > 1 && !image_offsets)
+    return fail(WPROJ_EINVAL, "image_offsets is required when n_images > 1");
+  int rc = check_device(k);
+  if (rc != WPROJ_OK) return rc;
+  const int64_t need = workspace_bytes_for(k, nvis);
+  if (workspace_bytes < need || (need > 0 && !workspace))
+    return fail(WPROJ_EWORKSPACE, "workspace of %lld bytes given, %lld needed",
+                (long long)workspace_bytes, (long long)need);
+  if (nvis == 0) return WPROJ_OK;
+  HIP_TRY(launch_plain_degrid(k, nvis, uvw, model_grid, image_offsets, vis_out, (hipStream_t)stream));
+  return WPROJ_OK;
+}
+
+int wproj_image(const wproj_kernels *k, int direction, void *grid, void *image,
+                const double *weight_sum, void *workspace, int64_t workspace_bytes, void *stream) {
+  g_err.clear();
+  if (!k) return fail(WPROJ_EINVAL, "handle is NULL");
+  if (!grid || !image) return fail(WPROJ_EINVAL, "grid and image are required");
+  if (direction == WPROJ_GRID_TO_IMAGE && !weight_sum)
+    return fail(WPROJ_EINVAL, "weight_sum is required for GRID_TO_IMAGE");
+  if (direction < WPROJ_GRID_TO_IMAGE || direction > WPROJ_GRID_TO_IMAGE_RAW)
+    return fail(WPROJ_EINVAL, "unknown direction %d", direction);
+  int rc = check_device(k);
+  if (rc != WPROJ_OK) return rc;
+  if (workspace_bytes < (int64_t)k->fft_work_bytes || (k->fft_work_bytes > 0 && !workspace))
+    return fail(WPROJ_EWORKSPACE, "workspace of %lld bytes given, %lld needed",
+                (long long)workspace_bytes, (long long)k->fft_work_bytes);
+  hipStream_t s = (hipStream_t)stream;
+  rocfft_execution_info info = nullptr;
+  if (rocfft_execution_info_create(&info) != rocfft_status_success)
+    return fail(WPROJ_EFFT, "rocfft_execution_info_create failed");
+  struct InfoGuard {
+    rocfft_execution_info i;
+    ~InfoGuard() { rocfft_execution_info_destroy(i); }
+  } ig{info};
+  rocfft_execution_info_set_stream(info, s);
+  if (k->fft_work_bytes > 0) rocfft_execution_info_set_work_buffer(info, workspace, k->fft_work_bytes);
+  void *buf[1] = {grid};
+  if (direction == WPROJ_IMAGE_TO_GRID) {
+    HIP_TRY(launch_i2g_precorrect(k, image, grid, s));
+    if (rocfft_execute(k->fft_fwd, buf, nullptr, info) != rocfft_status_success)
+      return fail(WPROJ_EFFT, "rocfft_execute (forward) failed");
+    return WPROJ_OK;
+  }
+  if (rocfft_execute(k->fft_inv, buf, nullptr, info) != rocfft_status_success)
+    return fail(WPROJ_EFFT, "rocfft_execute (inverse) failed");
+  HIP_TRY(launch_g2i_correct(k, grid, image, direction == WPROJ_GRID_TO_IMAGE ? weight_sum : nullptr, s));
+  return WPROJ_OK;
+}
+
+}  // extern "C"

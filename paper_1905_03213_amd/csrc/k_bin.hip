@@ -1,0 +1,284 @@
+// Device binning of visibilities by (image, uv-tile, w-plane): a counting sort.
+//
+// The paper's GPU path regroups rows before gridding: a key per row (its baseline
+// index, Eq. 5), a count array C per key, an exclusive prefix sum of C giving each
+// key's first position (Eq. 6), then a reorder.  The same counting-sort pattern is
+// used here, re-keyed so that each group is a uv-tile of the grid (and, within it,
+// one w-plane) that a workgroup can accumulate in LDS:
+//   key pass     classify each visibility, key = ((img * nty + ty) * ntx + tx) * kw + p,
+//                count[key] += 1 returning the visibility's slot within its key;
+//                also sumW per image and the drop/clamp/bad-weight counters;
+//   scan         exclusive prefix sum of count (Eq. 6);
+//   scatter      record of visibility j goes to offset[key] + slot;
+//   work list    each tile's record range split into chunks of at most `chunk` records.
+// Count atomics are aggregated across each wavefront's lanes that share a key.
+#include "wproj_tiled.h"
+
+namespace wproj {
+namespace {
+
+constexpr uint32_t kInvalid = 0xffffffffu;
+
+__device__ inline uint64_t lane_mask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Wave-aggregated atomicAdd(count[key], 1): returns this lane's slot.  Lanes with
+// key == kInvalid take no part.
+__device__ inline uint32_t aggregated_slot(uint32_t *count, uint32_t key) {
+  uint64_t pending = __ballot(key != kInvalid);
+  uint32_t slot = 0;
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t lk = __shfl(key, leader, 64);
+    const uint64_t same = __ballot(key == lk) & pending;
+    uint32_t base = 0;
+    if ((threadIdx.x & 63) == leader) base = atomicAdd(&count[lk], (uint32_t)__popcll(same));
+    base = __shfl(base, leader, 64);
+    if (key == lk) slot = base + (uint32_t)__popcll(same & lane_mask_lt());
+    pending &= ~same;
+  }
+  return slot;
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(256)
+    key_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
+               const Real *__restrict__ wt, const int64_t *__restrict__ img_off,
+               uint32_t *__restrict__ keys, uint32_t *__restrict__ slots, uint32_t *count,
+               double *wsum, unsigned long long *counters) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t key = kInvalid;
+  int cls = kFlagged;
+  int img = -1;
+  bool clamped = false;
+  double w = 0.0;
+  if (j < nvis) {
+    img = image_of(img_off, G.n_images, j);
+    if (img >= 0) {
+      Footprint f;
+      const Real wj = wt[j];
+      cls = classify(G, uvw + 3 * j, wj, f);
+      if (cls == kGridded) {
+        const int tx = f.x0 / B.tile, ty = f.y0 / B.tile;
+        key = (uint32_t)((((int64_t)img * B.nty + ty) * B.ntx + tx) * B.kw + (B.kw > 1 ? f.p : 0));
+        w = (double)wj;
+        clamped = G.n_w > 1 && fabs(uvw[3 * j + 2]) > G.w_max;
+      }
+    }
+  }
+  const uint32_t slot = aggregated_slot(count, key);
+  if (j < nvis) {
+    keys[j] = key;
+    slots[j] = slot;
+  }
+  // counters
+  const uint64_t dropped = __ballot(cls == kDropped);
+  const uint64_t bad = __ballot(cls == kBadWeight);
+  const uint64_t clamp = __ballot(clamped);
+  if ((threadIdx.x & 63) == 0 && counters) {
+    if (dropped) atomicAdd(&counters[0], (unsigned long long)__popcll(dropped));
+    if (clamp) atomicAdd(&counters[1], (unsigned long long)__popcll(clamp));
+    if (bad) atomicAdd(&counters[2], (unsigned long long)__popcll(bad));
+  }
+  // sum of weights per image, one atomic per distinct image in the wave
+  if (wsum) {
+    const int gimg = key != kInvalid ? img : -1;
+    uint64_t pending = __ballot(gimg >= 0);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const int li = __shfl(gimg, leader, 64);
+      const uint64_t same = __ballot(gimg == li) & pending;
+      const double s = wave_sum(gimg == li ? w : 0.0);
+      if ((threadIdx.x & 63) == leader) unsafeAtomicAdd(&wsum[li], s);
+      pending &= ~same;
+    }
+  }
+}
+
+template <typename Real, typename Cplx, typename Rec>
+__global__ void __launch_bounds__(256)
+    scatter_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
+                   const Cplx *__restrict__ vis, const Real *__restrict__ wt,
+                   const int64_t *__restrict__ img_off, const uint32_t *__restrict__ keys,
+                   const uint32_t *__restrict__ slots, const uint32_t *__restrict__ offset,
+                   Rec *__restrict__ rec) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nvis) return;
+  const uint32_t key = keys[j];
+  if (key == kInvalid) return;
+  Footprint f;
+  const Real w = wt[j];
+  classify(G, uvw + 3 * j, w, f);  // same inputs, same outcome as the key pass
+  const Cplx v = vis[j];
+  const int S = G.supp[f.p];
+  Rec r;
+  r.xy = (uint32_t)f.x0 | ((uint32_t)f.y0 << 16);
+  r.tap = (uint32_t)(G.tab_off[f.p] + ((int64_t)f.ov * G.O + f.ou) * S * S) |
+          ((uint32_t)(S - 1) << kTapBits);
+  r.wr = w * v.x;
+  r.wi = w * v.y;
+  rec[offset[key] + slots[j]] = r;
+}
+
+// ---- exclusive scan of uint32 counts (three phases) ----
+constexpr int kScanBlock = 1024;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
+  // Hillis-Steele over the block in LDS (1024 entries)
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    uint32_t add = t >= off ? sh[t - off] : 0u;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  total = sh[kScanBlock - 1];
+  uint32_t incl = sh[t];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(kScanBlock)
+    scan_tiles_kernel(const uint32_t *__restrict__ in, uint32_t *__restrict__ out, int64_t n,
+                      uint32_t *__restrict__ tile_sums) {
+  __shared__ uint32_t sh[kScanBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = base + i < n ? in[base + i] : 0u;
+    s += v[i];
+  }
+  uint32_t total;
+  uint32_t ex = block_exclusive_scan(s, sh, total);
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = ex;
+    ex += v[i];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// Scans the per-tile sums in place (one block, any count) and writes the grand total.
+__global__ void __launch_bounds__(kScanBlock)
+    scan_sums_kernel(uint32_t *sums, int64_t n_tiles, uint32_t *total_out) {
+  __shared__ uint32_t sh[kScanBlock];
+  uint32_t carry = 0;
+  for (int64_t b = 0; b < n_tiles; b += kScanBlock) {
+    const int64_t i = b + threadIdx.x;
+    const uint32_t v = i < n_tiles ? sums[i] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(v, sh, total);
+    if (i < n_tiles) sums[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ void __launch_bounds__(256)
+    scan_add_kernel(uint32_t *out, int64_t n, const uint32_t *__restrict__ tile_prefix) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += tile_prefix[i / kScanTile];
+}
+
+__global__ void __launch_bounds__(256)
+    chunk_count_kernel(const uint32_t *__restrict__ offset, int64_t n_tiles, int kw, int chunk,
+                       uint32_t *__restrict__ nch) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const uint32_t b = offset[t * kw], e = offset[(t + 1) * kw];
+  nch[t] = (e - b + (uint32_t)chunk - 1) / (uint32_t)chunk;
+}
+
+__global__ void __launch_bounds__(256)
+    chunk_emit_kernel(const uint32_t *__restrict__ offset, int64_t n_tiles, int kw, int chunk,
+                      const uint32_t *__restrict__ choff, WorkItem *__restrict__ items) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const uint32_t b = offset[t * kw], e = offset[(t + 1) * kw];
+  uint32_t o = choff[t];
+  for (uint32_t s = b; s < e; s += (uint32_t)chunk, ++o) {
+    WorkItem w;
+    w.tile = (uint32_t)t;
+    w.begin = s;
+    w.end = min(e, s + (uint32_t)chunk);
+    items[o] = w;
+  }
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+int64_t scan_temp_words(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+// out[i] = sum_{k < i} in[i], out[n] = total (out has n + 1 entries).
+hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
+                                 hipStream_t s) {
+  const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)tiles), dim3(kScanBlock), 0, s, in, out, n,
+                     tmp);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kScanBlock), 0, s, tmp, tiles, out + n);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, out, n, tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, const double *uvw,
+                      const void *vis, const void *wt, const int64_t *img_off, double *wsum,
+                      int64_t *counters, const BinWorkspace &W, hipStream_t s) {
+  const Geometry &G = k->geo;
+  auto *cnt = reinterpret_cast<unsigned long long *>(counters);
+  hipError_t e = launch_fill_u32(W.count, B.n_keys, 0u, s);
+  if (e != hipSuccess) return e;
+  const dim3 grid(nblk(nvis, 256)), block(256);
+  if (k->params.precision == WPROJ_F64) {
+    hipLaunchKernelGGL(key_kernel<double>, grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
+                       img_off, W.keys, W.slots, W.count, wsum, cnt);
+  } else {
+    hipLaunchKernelGGL(key_kernel<float>, grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
+                       img_off, W.keys, W.slots, W.count, wsum, cnt);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_exclusive_scan(W.count, W.offset, B.n_keys, W.scan_tmp, s)) != hipSuccess) return e;
+  if (k->params.precision == WPROJ_F64) {
+    hipLaunchKernelGGL((scatter_kernel<double, double2, RecordF64>), grid, block, 0, s, G, B, nvis,
+                       uvw, (const double2 *)vis, (const double *)wt, img_off, W.keys, W.slots,
+                       W.offset, (RecordF64 *)W.rec);
+  } else {
+    hipLaunchKernelGGL((scatter_kernel<float, float2, RecordF32>), grid, block, 0, s, G, B, nvis,
+                       uvw, (const float2 *)vis, (const float *)wt, img_off, W.keys, W.slots,
+                       W.offset, (RecordF32 *)W.rec);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // work list: per tile, ceil(records / chunk) items
+  hipLaunchKernelGGL(chunk_count_kernel, dim3(nblk(B.n_tiles, 256)), dim3(256), 0, s, W.offset,
+                     B.n_tiles, B.kw, B.chunk, W.nch);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_exclusive_scan(W.nch, W.choff, B.n_tiles, W.scan_tmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(chunk_emit_kernel, dim3(nblk(B.n_tiles, 256)), dim3(256), 0, s, W.offset,
+                     B.n_tiles, B.kw, B.chunk, W.choff, W.items);
+  return hipGetLastError();
+}
+
+}  // namespace wproj

@@ -1,0 +1,183 @@
+// Plain gridder and degridder: no binning, every tap goes straight to the grid in HBM
+// with a global atomic add (gridding) or a gather (degridding).  This is the direct
+// form of the paper's GPU gridding step (Section 2.2: threads over convolution taps,
+// atomic writes to global memory) and serves as the comparison path for the tiled
+// gridder; in FP64 it is the double-precision baseline.
+//
+// One 64-lane wavefront owns a contiguous range of visibilities and handles them one
+// at a time, its lanes covering the S_p x S_p taps (64 at a time).
+#include "wproj_internal.h"
+
+namespace wproj {
+namespace {
+
+__device__ inline double2 load_tap(const double2 *t, int64_t i) { return t[i]; }
+__device__ inline float2 load_tap(const float2 *t, int64_t i) { return t[i]; }
+__device__ inline float2 load_tap(const half2c *t, int64_t i) {
+  half2c h = t[i];
+  return make_float2((float)h.re, (float)h.im);
+}
+
+template <typename Real, typename Cplx, typename Tab>
+__global__ void __launch_bounds__(256)
+    plain_grid_kernel(Geometry G, const Tab *__restrict__ tab, int64_t nvis,
+                      const double *__restrict__ uvw, const Cplx *__restrict__ vis,
+                      const Real *__restrict__ wt, const int64_t *__restrict__ img_off,
+                      Real *grid, double *wsum, unsigned long long *counters, int64_t per_wave) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t j0 = wave * per_wave;
+  const int64_t j1 = min(nvis, j0 + per_wave);
+  const int64_t cells = (int64_t)G.n * G.n;
+  double wacc = 0.0;
+  int wimg = -1;
+  unsigned long long c_drop = 0, c_clamp = 0, c_bad = 0;
+  for (int64_t j = j0; j < j1; ++j) {
+    const int img = image_of(img_off, G.n_images, j);
+    if (img < 0) continue;
+    const Real w = wt[j];
+    Footprint f;
+    const int c = classify(G, uvw + 3 * j, w, f);
+    if (c != kGridded) {
+      c_drop += (c == kDropped);
+      c_bad += (c == kBadWeight);
+      continue;
+    }
+    if (G.n_w > 1 && fabs(uvw[3 * j + 2]) > G.w_max) ++c_clamp;
+    if (img != wimg) {
+      if (wimg >= 0 && wsum && lane == 0) unsafeAtomicAdd(&wsum[wimg], wacc);
+      wacc = 0.0;
+      wimg = img;
+    }
+    wacc += (double)w;
+    const Cplx v = vis[j];
+    const Real ar = w * v.x, ai = w * v.y;
+    const int S = G.supp[f.p];
+    const Tab *T = tab + G.tab_off[f.p] + ((int64_t)f.ov * G.O + f.ou) * S * S;
+    Real *gimg = grid + 2 * cells * img;
+    for (int t = lane; t < S * S; t += 64) {
+      const int kv = t / S, ku = t - kv * S;
+      const auto k = load_tap(T, t);
+      const Real gr = ar * k.x - ai * k.y;
+      const Real gi = ar * k.y + ai * k.x;
+      const int64_t cell = (int64_t)(f.y0 + kv) * G.n + (f.x0 + ku);
+      unsafeAtomicAdd(&gimg[2 * cell], gr);
+      unsafeAtomicAdd(&gimg[2 * cell + 1], gi);
+    }
+  }
+  if (lane == 0) {
+    if (wimg >= 0 && wsum) unsafeAtomicAdd(&wsum[wimg], wacc);
+    if (counters) {
+      if (c_drop) atomicAdd(&counters[0], c_drop);
+      if (c_clamp) atomicAdd(&counters[1], c_clamp);
+      if (c_bad) atomicAdd(&counters[2], c_bad);
+    }
+  }
+}
+
+template <typename Real, typename Cplx, typename Tab>
+__global__ void __launch_bounds__(256)
+    plain_degrid_kernel(Geometry G, const Tab *__restrict__ tab, int64_t nvis,
+                        const double *__restrict__ uvw, const Cplx *__restrict__ grid,
+                        const int64_t *__restrict__ img_off, Cplx *__restrict__ out,
+                        int64_t per_wave) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t j0 = wave * per_wave;
+  const int64_t j1 = min(nvis, j0 + per_wave);
+  const int64_t cells = (int64_t)G.n * G.n;
+  for (int64_t j = j0; j < j1; ++j) {
+    const int img = image_of(img_off, G.n_images, j);
+    Footprint f;
+    Real re = 0, im = 0;
+    if (img >= 0 && classify(G, uvw + 3 * j, 1.0, f) == kGridded) {
+      const int S = G.supp[f.p];
+      const Tab *T = tab + G.tab_off[f.p] + ((int64_t)f.ov * G.O + f.ou) * S * S;
+      const Cplx *gimg = grid + cells * img;
+      for (int t = lane; t < S * S; t += 64) {
+        const int kv = t / S, ku = t - kv * S;
+        const auto k = load_tap(T, t);
+        const Cplx m = gimg[(int64_t)(f.y0 + kv) * G.n + (f.x0 + ku)];
+        re += k.x * m.x + k.y * m.y;  // conj(k) * m
+        im += k.x * m.y - k.y * m.x;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off, 64);
+      im += __shfl_xor(im, off, 64);
+    }
+    if (lane == 0) {
+      Cplx o;
+      o.x = re;
+      o.y = im;
+      out[j] = o;
+    }
+  }
+}
+
+inline void plain_shape(int64_t nvis, unsigned &blocks, int64_t &per_wave) {
+  const int64_t max_waves = 256 * 32;  // 256 CUs x 32 waves
+  int64_t waves = nvis < max_waves ? (nvis > 0 ? nvis : 1) : max_waves;
+  per_wave = (nvis + waves - 1) / waves;
+  if (per_wave < 1) per_wave = 1;
+  waves = (nvis + per_wave - 1) / per_wave;
+  if (waves < 1) waves = 1;
+  blocks = (unsigned)((waves + 3) / 4);  // 4 waves per 256-thread block
+}
+
+}  // namespace
+
+hipError_t launch_plain_grid(const wproj_kernels *k, int64_t nvis, const double *uvw,
+                             const void *vis, const void *wt, const int64_t *img_off, void *grid,
+                             double *wsum, int64_t *counters, hipStream_t s) {
+  unsigned blocks;
+  int64_t per_wave;
+  plain_shape(nvis, blocks, per_wave);
+  auto *cnt = reinterpret_cast<unsigned long long *>(counters);
+  switch (k->params.precision) {
+    case WPROJ_F64:
+      hipLaunchKernelGGL((plain_grid_kernel<double, double2, double2>), dim3(blocks), dim3(256), 0,
+                         s, k->geo, (const double2 *)k->d_tab, nvis, uvw, (const double2 *)vis,
+                         (const double *)wt, img_off, (double *)grid, wsum, cnt, per_wave);
+      break;
+    case WPROJ_F32:
+      hipLaunchKernelGGL((plain_grid_kernel<float, float2, float2>), dim3(blocks), dim3(256), 0, s,
+                         k->geo, (const float2 *)k->d_tab, nvis, uvw, (const float2 *)vis,
+                         (const float *)wt, img_off, (float *)grid, wsum, cnt, per_wave);
+      break;
+    default:
+      hipLaunchKernelGGL((plain_grid_kernel<float, float2, half2c>), dim3(blocks), dim3(256), 0, s,
+                         k->geo, (const half2c *)k->d_tab, nvis, uvw, (const float2 *)vis,
+                         (const float *)wt, img_off, (float *)grid, wsum, cnt, per_wave);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_degrid(const wproj_kernels *k, int64_t nvis, const double *uvw,
+                               const void *grid, const int64_t *img_off, void *vis_out,
+                               hipStream_t s) {
+  unsigned blocks;
+  int64_t per_wave;
+  plain_shape(nvis, blocks, per_wave);
+  switch (k->params.precision) {
+    case WPROJ_F64:
+      hipLaunchKernelGGL((plain_degrid_kernel<double, double2, double2>), dim3(blocks), dim3(256),
+                         0, s, k->geo, (const double2 *)k->d_tab, nvis, uvw,
+                         (const double2 *)grid, img_off, (double2 *)vis_out, per_wave);
+      break;
+    case WPROJ_F32:
+      hipLaunchKernelGGL((plain_degrid_kernel<float, float2, float2>), dim3(blocks), dim3(256), 0,
+                         s, k->geo, (const float2 *)k->d_tab, nvis, uvw, (const float2 *)grid,
+                         img_off, (float2 *)vis_out, per_wave);
+      break;
+    default:
+      hipLaunchKernelGGL((plain_degrid_kernel<float, float2, half2c>), dim3(blocks), dim3(256), 0,
+                         s, k->geo, (const half2c *)k->d_tab, nvis, uvw, (const float2 *)grid,
+                         img_off, (float2 *)vis_out, per_wave);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace wproj

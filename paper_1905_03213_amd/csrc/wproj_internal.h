@@ -1,0 +1,163 @@
+// Internal declarations of the gfx950 w-projection library: the handle, the
+// per-visibility footprint rule shared by every kernel, and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "wproj.h"
+
+namespace wproj {
+
+// Kernel tables stored at reduced precision: one FP16 pair per tap.
+struct alignas(4) half2c {
+  _Float16 re, im;
+};
+
+// Geometry every kernel needs, passed by value.
+struct Geometry {
+  int32_t n;        // grid side
+  int32_t O;        // oversampling
+  int32_t n_w;      // w-planes
+  int32_t n_images;
+  double fov;       // n * cell_rad
+  double w_max;
+  double dw;        // 2 w_max / (n_w - 1), 0 for a single plane
+  const int32_t *supp;     // device [n_w] full support per plane
+  const int64_t *tab_off;  // device [n_w + 1] first tap of each plane
+};
+
+enum VisClass { kGridded = 0, kFlagged = 1, kBadWeight = 2, kDropped = 3 };
+
+struct Footprint {
+  int x0, y0, ou, ov, p;
+};
+
+__device__ inline int64_t floor_div(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b) != 0 && ((a < 0) != (b < 0))) q -= 1;
+  return q;
+}
+
+// Nearest w-plane, ties rounding up, clamped to [0, n_w - 1].
+__device__ inline int plane_of(const Geometry &G, double w) {
+#pragma clang fp contract(off)
+  if (G.n_w == 1) return 0;
+  double t = floor((w + G.w_max) / G.dw + 0.5);
+  if (!(t >= 0.0)) return 0;
+  if (t > (double)(G.n_w - 1)) return G.n_w - 1;
+  return (int)t;
+}
+
+// One axis of the footprint: g = coord FoV + n/2 cells, q = floor(g O + 1/2) on the
+// 1/O lattice, first cell x0 = floor((q - S O/2)/O) + 1, sub-kernel ou = x0 O - q + S O/2 - 1.
+// Each product and sum rounds separately, so the integer outcome is a pure function of
+// the float64 inputs.  Returns false when the S cells do not all lie on the grid.
+__device__ inline bool axis_footprint(const Geometry &G, double coord, int S, int &x0, int &ou) {
+#pragma clang fp contract(off)
+  double g = coord * G.fov;
+  g = g + (double)G.n / 2.0;
+  double t = g * (double)G.O;
+  double qd = floor(t + 0.5);
+  if (!(fabs(qd) < 1e15)) return false;
+  int64_t q = (int64_t)qd;
+  int64_t half = (int64_t)S * G.O / 2;
+  int64_t a = floor_div(q - half, G.O) + 1;
+  if (a < 0 || a + S > G.n) return false;
+  x0 = (int)a;
+  ou = (int)(a * G.O - q + half - 1);
+  return true;
+}
+
+template <typename WT>
+__device__ inline int classify(const Geometry &G, const double *uvw, WT wt, Footprint &f) {
+  if (wt == WT(0)) return kFlagged;
+  if (!(isfinite((double)wt) && wt > WT(0))) return kBadWeight;
+  const double u = uvw[0], v = uvw[1], w = uvw[2];
+  if (!(isfinite(u) && isfinite(v) && isfinite(w))) return kDropped;
+  f.p = plane_of(G, w);
+  const int S = G.supp[f.p];
+  if (!axis_footprint(G, u, S, f.x0, f.ou)) return kDropped;
+  if (!axis_footprint(G, v, S, f.y0, f.ov)) return kDropped;
+  return kGridded;
+}
+
+// Image owning row j: the largest i with off[i] <= j, or -1 outside [off[0], off[n_images]).
+__device__ inline int image_of(const int64_t *off, int n_images, int64_t j) {
+  if (off == nullptr) return 0;
+  if (j < off[0] || j >= off[n_images]) return -1;
+  int lo = 0, hi = n_images - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= j)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace wproj
+
+// The opaque handle.
+struct wproj_kernels {
+  wproj_params params;  // copy; support_per_plane is cleared
+  int device = 0;
+  wproj::Geometry geo{};
+  std::vector<int32_t> supp_host;
+  std::vector<int64_t> tab_off_host;
+  int s_max = 0;
+  bool uniform_support = true;
+  int32_t *d_supp = nullptr;
+  int64_t *d_tab_off = nullptr;
+  void *d_tab = nullptr;  // double2 / float2 / half2c per tap
+  int64_t n_taps = 0;
+  size_t tap_bytes = 0;
+  double *d_kappa = nullptr;
+  double *d_taper = nullptr;
+  rocfft_plan fft_fwd = nullptr, fft_inv = nullptr;
+  size_t fft_work_bytes = 0;
+  int tile = 64;            // tiled gridder tile side
+  bool plane_in_key = true; // bin by (tile, plane) rather than tile alone
+  int chunk = 8192;         // max records per gridder work item
+  int n_cu = 256;           // compute units of the device
+  size_t max_lds = 65536;   // LDS bytes available to one workgroup
+};
+
+namespace wproj {
+
+// ---- launchers (each returns hipSuccess or the first launch error) ----
+
+// Table generation (FP64): taper/kappa evaluation from Legendre coefficients of psi_0.
+hipError_t launch_taper(const double *d_coef, int n_coef, int m, int n, double *d_taper,
+                        double *d_kappa, hipStream_t s);
+// Screen for planes [p0, p0 + np): out[p - p0][j][i] complex128.
+hipError_t launch_screen(const double *d_taper, int m, double fov, double w_max, double dw,
+                         int n_w, int p0, int np, double2 *out, hipStream_t s);
+// Row and column DFTs for planes [p0, p0 + np) into C[p - p0][ib][ia], stride so_max.
+hipError_t launch_table_dft(const double2 *screen, int m, int O, const int32_t *d_supp, int p0,
+                            int np, int so_max, double2 *tmp, double2 *C, hipStream_t s);
+// Normalise each sub-kernel and store it in the handle's precision.
+hipError_t launch_normalise(const double2 *C, int so_max, int O, const int32_t *d_supp,
+                            const int64_t *d_tab_off, int p0, int np, int precision, void *tab,
+                            hipStream_t s);
+
+// Plain (no binning) gridder / degridder.
+hipError_t launch_plain_grid(const wproj_kernels *k, int64_t nvis, const double *uvw,
+                             const void *vis, const void *wt, const int64_t *img_off, void *grid,
+                             double *wsum, int64_t *counters, hipStream_t s);
+hipError_t launch_plain_degrid(const wproj_kernels *k, int64_t nvis, const double *uvw,
+                               const void *grid, const int64_t *img_off, void *vis_out,
+                               hipStream_t s);
+
+// Image-plane kernels around the FFTs.
+hipError_t launch_g2i_correct(const wproj_kernels *k, const void *fgrid, void *image,
+                              const double *wsum, hipStream_t s);
+hipError_t launch_i2g_precorrect(const wproj_kernels *k, const void *image, void *grid,
+                                 hipStream_t s);
+
+}  // namespace wproj

@@ -1,0 +1,76 @@
+// Shapes and buffers of the binned (tiled) gridding path.
+#pragma once
+
+#include "wproj_internal.h"
+
+namespace wproj {
+
+// Bits of Record::tap holding the first tap of the visibility's sub-kernel; the top
+// bits hold S_p - 1.
+constexpr int kTapBits = 26;
+constexpr uint32_t kTapMask = (1u << kTapBits) - 1u;
+
+// One binned visibility: first cell (x0 | y0 << 16), sub-kernel (first tap | (S-1) << 26)
+// and W V at the path's precision.
+struct RecordF32 {
+  uint32_t xy;
+  uint32_t tap;
+  float wr, wi;
+};
+struct RecordF64 {
+  uint32_t xy;
+  uint32_t tap;
+  double wr, wi;
+};
+
+// Binning geometry: tiles of `tile` cells, ntx x nty per image, kw keys per tile
+// (n_wplanes when the plane is part of the key, else 1).
+struct BinShape {
+  int tile;
+  int ntx, nty;
+  int kw;
+  int chunk;         // max records per work item
+  int64_t n_tiles;   // n_images * ntx * nty
+  int64_t n_keys;    // n_tiles * kw
+};
+
+struct WorkItem {
+  uint32_t tile;   // img * (ntx * nty) + ty * ntx + tx
+  uint32_t begin;  // record range
+  uint32_t end;
+};
+
+// Workspace carve-up for one call (all device pointers).
+struct BinWorkspace {
+  uint32_t *keys;      // [nvis]
+  uint32_t *slots;     // [nvis]
+  void *rec;           // [nvis] RecordF32 / RecordF64
+  uint32_t *count;     // [n_keys]
+  uint32_t *offset;    // [n_keys + 1]
+  uint32_t *nch;       // [n_tiles]
+  uint32_t *choff;     // [n_tiles + 1]; choff[n_tiles] = number of work items
+  WorkItem *items;     // [max_items]
+  uint32_t *scan_tmp;  // scan_temp_words(max(n_keys, n_tiles))
+  uint32_t *counter;   // [1] work-queue head
+};
+
+int64_t scan_temp_words(int64_t n);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
+                                 hipStream_t s);
+hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, const double *uvw,
+                      const void *vis, const void *wt, const int64_t *img_off, double *wsum,
+                      int64_t *counters, const BinWorkspace &W, hipStream_t s);
+
+// LDS tile geometry of the tiled gridder for a handle.
+struct TileShape {
+  int tile;   // T
+  int rows;   // T + S_max - 1
+  int pitch;  // >= rows, padded for conflict-free rows of taps
+  size_t lds_bytes;
+};
+TileShape tile_shape(const wproj_kernels *k, int tile);
+hipError_t launch_tiled_grid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
+                             void *grid, hipStream_t s);
+
+}  // namespace wproj

@@ -1,0 +1,177 @@
+"""Python binding of the w-projection C ABI: argument marshalling only.
+
+Tensors are passed by device pointer (torch supplies memory and the current
+HIP stream); every step runs in the library's HIP kernels.  Function names
+follow the C entry points (wproj_make_kernels -> make_kernels, ...).
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import (ALGO_PLAIN, ALGO_TILED, F32, F32_F16TABLE, F64, GRID_TO_IMAGE,  # noqa: F401
+                   GRID_TO_IMAGE_RAW, IMAGE_TO_GRID, WprojError)
+
+_PREC = {"f64": F64, "f32": F32, "f32_f16table": F32_F16TABLE}
+_ALGO = {"tiled": ALGO_TILED, "plain": ALGO_PLAIN}
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t: Optional[torch.Tensor], name: str, dtype=None, numel=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, {numel} needed")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Kernels:
+    """A built handle (kernel tables, grid correction, FFT plans) and its parameters."""
+
+    def __init__(self, handle: ctypes.c_void_p, params: dict):
+        self.handle = handle
+        self.params = dict(params)
+        prec = self.params["precision"]
+        self.real = torch.float64 if prec == "f64" else torch.float32
+        self.cplx = torch.complex128 if prec == "f64" else torch.complex64
+
+    def free(self):
+        if self.handle:
+            _lib.lib().wproj_free_kernels(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def workspace_size(self, nvis: int) -> int:
+        r = _lib.lib().wproj_workspace_size(self.handle, int(nvis))
+        if r < 0:
+            _lib.check("wproj_workspace_size", int(r))
+        return int(r)
+
+    def workspace(self, nvis: int, device="cuda") -> torch.Tensor:
+        return torch.empty(max(1, self.workspace_size(nvis)), dtype=torch.uint8, device=device)
+
+    def export(self, what: int, stream=None) -> torch.Tensor:
+        L = _lib.lib()
+        need = ctypes.c_int64(0)
+        _lib.check("wproj_export", L.wproj_export(self.handle, int(what), None, 0,
+                                                   ctypes.byref(need), None))
+        out = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+        _lib.check("wproj_export", L.wproj_export(self.handle, int(what),
+                                                   ctypes.c_void_p(out.data_ptr()), need.value,
+                                                   None, _stream(stream)))
+        return out
+
+    def new_grid(self, device="cuda") -> torch.Tensor:
+        n, ni = self.params["n"], self.params.get("n_images", 1)
+        return torch.zeros((ni, n, n), dtype=self.cplx, device=device)
+
+
+def make_kernels(params: dict, stream=None) -> Kernels:
+    """wproj_make_kernels.  params keys: n, cell_rad, n_wplanes, w_max, support,
+    support_per_plane (list or None), oversample, kernel_image_size, precision
+    ("f64" | "f32" | "f32_f16table"), n_images, algorithm ("tiled" | "plain"), tile."""
+    P = _lib.Params()
+    P.n = int(params["n"])
+    P.n_wplanes = int(params["n_wplanes"])
+    P.cell_rad = float(params["cell_rad"])
+    P.w_max = float(params["w_max"])
+    P.support = int(params["support"])
+    P.oversample = int(params["oversample"])
+    spp = params.get("support_per_plane")
+    keep = None
+    if spp is not None:
+        keep = (ctypes.c_int32 * len(spp))(*[int(s) for s in spp])
+        P.support_per_plane = keep
+    P.kernel_image_size = int(params["kernel_image_size"])
+    prec = params.get("precision", "f32")
+    P.precision = _PREC[prec] if isinstance(prec, str) else int(prec)
+    P.n_images = int(params.get("n_images", 1))
+    algo = params.get("algorithm", "tiled")
+    P.algorithm = _ALGO[algo] if isinstance(algo, str) else int(algo)
+    P.tile = int(params.get("tile", 0))
+    h = ctypes.c_void_p()
+    _lib.check("wproj_make_kernels",
+               _lib.lib().wproj_make_kernels(ctypes.byref(P), _stream(stream), ctypes.byref(h)))
+    del keep
+    p = dict(params)
+    p.setdefault("precision", "f32")
+    p.setdefault("n_images", 1)
+    return Kernels(h, p)
+
+
+def grid(k: Kernels, uvw: torch.Tensor, vis: torch.Tensor, weight: torch.Tensor,
+         grid_out: torch.Tensor, image_offsets: Optional[torch.Tensor] = None,
+         weight_sum: Optional[torch.Tensor] = None, counters: Optional[torch.Tensor] = None,
+         workspace: Optional[torch.Tensor] = None, stream=None):
+    """wproj_grid: grid_out += gridded visibilities (weight_sum, counters accumulated)."""
+    nvis = int(uvw.shape[0]) if uvw.dim() else 0
+    n, ni = k.params["n"], k.params.get("n_images", 1)
+    if workspace is None:
+        workspace = k.workspace(nvis)
+    _lib.check("wproj_grid", _lib.lib().wproj_grid(
+        k.handle, nvis, _ptr(uvw, "uvw", torch.float64, 3 * nvis), _ptr(vis, "vis", k.cplx, nvis),
+        _ptr(weight, "weight", k.real, nvis),
+        _ptr(image_offsets, "image_offsets", torch.int64, ni + 1),
+        _ptr(grid_out, "grid", k.cplx, ni * n * n),
+        _ptr(weight_sum, "weight_sum", torch.float64, ni),
+        _ptr(counters, "counters", torch.int64, 3),
+        _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
+
+
+def degrid(k: Kernels, uvw: torch.Tensor, model_grid: torch.Tensor, vis_out: torch.Tensor,
+           image_offsets: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+           stream=None):
+    """wproj_degrid: vis_out = prediction from the model grid."""
+    nvis = int(uvw.shape[0])
+    n, ni = k.params["n"], k.params.get("n_images", 1)
+    if workspace is None:
+        workspace = k.workspace(nvis)
+    _lib.check("wproj_degrid", _lib.lib().wproj_degrid(
+        k.handle, nvis, _ptr(uvw, "uvw", torch.float64, 3 * nvis),
+        _ptr(model_grid, "model_grid", k.cplx, ni * n * n),
+        _ptr(image_offsets, "image_offsets", torch.int64, ni + 1),
+        _ptr(vis_out, "vis_out", k.cplx, nvis),
+        _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
+
+
+def image(k: Kernels, direction: int, grid_buf: torch.Tensor, image_buf: torch.Tensor,
+          weight_sum: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+          stream=None):
+    """wproj_image: GRID_TO_IMAGE(_RAW) transforms grid_buf in place into image_buf;
+    IMAGE_TO_GRID overwrites grid_buf from image_buf."""
+    n, ni = k.params["n"], k.params.get("n_images", 1)
+    if workspace is None:
+        workspace = k.workspace(0)
+    _lib.check("wproj_image", _lib.lib().wproj_image(
+        k.handle, int(direction), _ptr(grid_buf, "grid", k.cplx, ni * n * n),
+        _ptr(image_buf, "image", k.real, ni * n * n),
+        _ptr(weight_sum, "weight_sum", torch.float64, ni),
+        _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
+
+
+def last_error() -> str:
+    return _lib.lib().wproj_last_error().decode()
+
+
+def version() -> int:
+    return int(_lib.lib().wproj_version())

@@ -1,0 +1,73 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared entry
+point, and rejects bad arguments before touching the GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1905_03213_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "wproj.h")).read()
+    return sorted(set(re.findall(r"^\S[^\n(]*?\b(wproj_\w+)\(", src, re.M)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(_lib.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert L.wproj_version() >= 100
+
+
+def _params(**kw):
+    P = _lib.Params()
+    base = dict(n=64, n_wplanes=3, cell_rad=1e-3, w_max=10.0, support=7, oversample=8,
+                kernel_image_size=32, precision=_lib.F32, n_images=1, algorithm=0, tile=0)
+    base.update(kw)
+    for k, v in base.items():
+        setattr(P, k, v)
+    return P
+
+
+@pytest.mark.parametrize("bad", [dict(n=63), dict(cell_rad=0.1), dict(n_wplanes=0),
+                                 dict(w_max=-1.0), dict(support=0), dict(support=7, oversample=1),
+                                 dict(kernel_image_size=31), dict(precision=7), dict(n_images=0),
+                                 dict(algorithm=5), dict(tile=48)])
+def test_make_kernels_rejects_invalid_params(bad):
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    rc = L.wproj_make_kernels(ctypes.byref(_params(**bad)), None, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    assert L.wproj_last_error()
+
+
+def test_reserved_and_per_plane_support_checked():
+    L = _lib.lib()
+    P = _params()
+    P.reserved[2] = 1
+    h = ctypes.c_void_p()
+    assert L.wproj_make_kernels(ctypes.byref(P), None, ctypes.byref(h)) == -1
+    P = _params()
+    spp = (ctypes.c_int32 * 3)(7, 33, 7)
+    P.support_per_plane = spp
+    assert L.wproj_make_kernels(ctypes.byref(P), None, ctypes.byref(h)) == -1
+    assert b"support" in L.wproj_last_error()
+
+
+def test_null_handle_paths():
+    L = _lib.lib()
+    assert L.wproj_workspace_size(None, 10) == -1
+    assert L.wproj_grid(None, 0, None, None, None, None, None, None, None, None, 0, None) == -1
+    assert L.wproj_degrid(None, 0, None, None, None, None, None, 0, None) == -1
+    assert L.wproj_image(None, 0, None, None, None, None, 0, None) == -1
+    assert L.wproj_export(None, 0, None, 0, None, None) == -1
+    assert L.wproj_free_kernels(None) == 0
