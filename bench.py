@@ -1,0 +1,245 @@
+"""Benchmark: gridded visibilities per second for w-projection imaging on one MI355X.
+
+Workload: a 2048^2 grid with 1e-5 rad cells; 27 antennas in a 10 km-radius disk
+(351 baselines), an 8 h track at 10 s, dec +45 deg, 64 channels over 1.0-1.5 GHz
+(6.47e7 visibilities, synthetic and resident in HBM before timing); 128 w-planes,
+support 8, oversampling 8, 50 point sources plus noise.
+
+One step = one pass of the imaging hot path on that batch, FP32 with the binned
+LDS-tile gridder: zero the grid, wproj_grid (key/count, scan, scatter, work list,
+tile gridder, sum of weights), then wproj_image (inverse FFT and grid correction).
+value = on-grid visibilities / step time, in Mvis/s.  Beside it: the FP64 plain
+gridder (the double-precision comparison path), degridding of the same
+visibilities, per-phase times from HIP events, the roofline of the dominant kernel
+and the FP64 oracle timed on the host.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks and a derived LDS bandwidth (see the roofline notes in the
+# design document): 256 CUs x 128 B/clk x 2.4 GHz.
+PEAK_HBM = 8.0e12
+PEAK_LDS = 256 * 128 * 2.4e9
+PEAK_FP32 = 157.3e12
+S = 8
+LDS_BYTES_PER_VIS = S * S * 16   # complex FP32 read-modify-write per tap
+FLOPS_PER_VIS = S * S * 8        # complex multiply-add per tap
+HBM_BYTES_PER_VIS_GRID = 16      # one binned record read by the tile gridder
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--hours", type=float, default=8.0, help="track length (default: full 8 h)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build grids one GPU's share of the "
+              "visibilities and has no multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1905_03213_amd as W
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    wl = synth.cfg2(device=dev, precision="f32", hours=args.hours)
+    nvis = wl.nvis
+    uvw = wl.uvw
+    vis32 = wl.vis.to(torch.complex64)
+    wt32 = wl.weight.to(torch.float32)
+    log(f"workload: {nvis} visibilities generated in {time.time() - t0:.1f} s")
+
+    params = {**wl.params, "precision": "f32", "algorithm": "tiled"}
+    k = W.make_kernels(params)
+    n = params["n"]
+    g = k.new_grid()
+    img = torch.empty((1, n, n), dtype=torch.float32, device=dev)
+    ws = k.workspace(nvis)
+    sw = torch.zeros(1, dtype=torch.float64, device=dev)
+    cnt = torch.zeros(3, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        g.zero_()
+        sw.zero_()
+        cnt.zero_()
+        W.grid(k, uvw, vis32, wt32, g, weight_sum=sw, counters=cnt, workspace=ws)
+        W.image(k, W.GRID_TO_IMAGE, g, img, sw, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    n_valid = int(round(sw.item()))  # unit weights: sum of weights = gridded count
+    counters = cnt.cpu().tolist()
+    k.profile(True)
+    k.profile_read()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    phases = k.profile_read()
+    k.profile(False)
+    ms_step = ms_total / args.steps
+    value = n_valid / (ms_step * 1e-3) / 1e6
+    per = {name: ms / max(c, 1) for name, (ms, c) in phases.items() if c}
+    log(f"fp32 tiled: {ms_step:.3f} ms/step, {value:.1f} Mvis/s, phases {per}")
+
+    t_grid = per["grid"] * 1e-3
+    achieved_lds = LDS_BYTES_PER_VIS * n_valid / t_grid
+    roofline = {
+        "bound": "lds",
+        "kernel": "tiled_grid_kernel",
+        "achieved": achieved_lds / 1e9,
+        "peak": PEAK_LDS / 1e9,
+        "unit": "GB/s",
+        "frac": achieved_lds / PEAK_LDS,
+        "traffic": None,
+        "per_unit": {"unit": "on-grid visibility", "lds_bytes": LDS_BYTES_PER_VIS,
+                     "flops": FLOPS_PER_VIS, "hbm_bytes": HBM_BYTES_PER_VIS_GRID},
+        "units_per_launch": n_valid,
+        "alu_frac": FLOPS_PER_VIS * n_valid / t_grid / PEAK_FP32,
+        "hbm_frac": HBM_BYTES_PER_VIS_GRID * n_valid / t_grid / PEAK_HBM,
+    }
+
+    # degridding of the same visibilities from the imaged model (adjoint direction)
+    vout = torch.empty(nvis, dtype=torch.complex64, device=dev)
+    W.image(k, W.IMAGE_TO_GRID, g, img, workspace=ws)
+    W.degrid(k, uvw, g, vout, workspace=ws)
+    torch.cuda.synchronize()
+    k.profile(True)
+    reps = max(2, args.steps // 4)
+    for _ in range(reps):
+        W.degrid(k, uvw, g, vout, workspace=ws)
+    torch.cuda.synchronize()
+    dph = k.profile_read()
+    k.profile(False)
+    degrid_ms = dph["degrid"][0] / max(dph["degrid"][1], 1)
+
+    extra = {"phases_ms": per, "degrid": {"ms": degrid_ms, "mvis_per_s": n_valid / degrid_ms / 1e3},
+             "counters": {"dropped": counters[0], "w_clamped": counters[1], "bad_weight": counters[2]},
+             "nvis_total": nvis, "nvis_gridded": n_valid}
+    del ws
+    k.free()
+
+    if not args.no_fp64:
+        p64 = {**wl.params, "precision": "f64", "algorithm": "plain"}
+        k64 = W.make_kernels(p64)
+        g64 = k64.new_grid()
+        ws64 = k64.workspace(nvis)
+        wt64 = wl.weight
+        vis64 = wl.vis
+        W.grid(k64, uvw, vis64, wt64, g64, workspace=ws64)
+        torch.cuda.synchronize()
+        k64.profile(True)
+        reps = 2
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            g64.zero_()
+            W.grid(k64, uvw, vis64, wt64, g64, workspace=ws64)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        p = k64.profile_read()
+        ms64 = p["plain"][0] / max(p["plain"][1], 1)
+        extra["fp64_plain"] = {"ms": ms64, "mvis_per_s": n_valid / ms64 / 1e3,
+                               "speedup_fp32_tiled_grid_vs_fp64_plain": ms64 / (per["bin"] + per["grid"])}
+        log(f"fp64 plain: {ms64:.2f} ms, {n_valid / ms64 / 1e3:.1f} Mvis/s")
+        del g64, ws64
+        k64.free()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+        log(f"cpu baseline: {cpu}")
+
+    out = {
+        "metric": "gridded Mvis/s at S=8, 2048^2 grid (FP32 tiled, vs FP64 plain GPU); % of roofline",
+        "value": value,
+        "unit": "Mvis/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "w-projection gridding + FFT + correction: 2048^2 grid, cell 1e-5 rad, "
+                               "27-antenna 8 h track at 10 s, 64 channels 1.0-1.5 GHz "
+                               f"({nvis} visibilities), 128 w-planes, S=8, oversampling 8",
+                   "n": n, "nvis": nvis, "n_wplanes": 128, "support": 8, "oversample": 8,
+                   "kernel_image_size": params["kernel_image_size"], "tile": 64,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(wl, seconds):
+    """The plain C FP64 oracle gridder on the host's cores, on a bounded prefix of the
+    same visibilities, sized to about `seconds` of work."""
+    import numpy as np
+
+    from oracle import cref
+    from oracle import wproj_ref as R
+
+    plan = R.Plan({**wl.params, "precision": "f64"})
+    tabs = R.kernel_tables(plan)
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = max(1, min(threads, int(os.environ.get("OMP_NUM_THREADS", threads))))
+    # calibrate on a small prefix, then size the timed sample
+    n0 = 200_000
+    u = wl.uvw[:n0].cpu().numpy()
+    v = wl.vis[:n0].cpu().numpy()
+    w = wl.weight[:n0].cpu().numpy()
+    t = time.time()
+    cref.grid(plan, tabs, u, v, w, nthreads=threads)
+    rate = n0 / max(time.time() - t, 1e-3)
+    ns = int(min(wl.nvis, max(n0, rate * seconds)))
+    u = wl.uvw[:ns].cpu().numpy()
+    v = wl.vis[:ns].cpu().numpy()
+    w = wl.weight[:ns].cpu().numpy()
+    t = time.time()
+    _, sw, _ = cref.grid(plan, tabs, u, v, w, nthreads=threads)
+    dt = time.time() - t
+    return {"value": float(sw[0]) / dt / 1e6, "unit": "Mvis/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {ns} of {wl.nvis} visibilities (MS order), FP64 C oracle gridder, "
+                      f"OpenMP per-thread grids, {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

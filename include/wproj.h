@@ -186,6 +186,30 @@ typedef enum {
 int wproj_image(const wproj_kernels *k, int direction, void *grid, void *image,
                 const double *weight_sum, void *workspace, int64_t workspace_bytes, void *stream);
 
+/* Phases timed by wproj_profile. */
+typedef enum {
+  WPROJ_PHASE_BIN = 0,      /* key/count, scan, scatter, work list (tiled gridding) */
+  WPROJ_PHASE_GRID = 1,     /* the LDS-tile gridder kernel */
+  WPROJ_PHASE_PLAIN = 2,    /* the plain gridder kernel */
+  WPROJ_PHASE_FFT = 3,      /* rocFFT execution inside wproj_image */
+  WPROJ_PHASE_CORRECT = 4,  /* grid-correction / pre-correction kernel of wproj_image */
+  WPROJ_PHASE_DEGRID = 5,   /* the degridder kernel */
+  WPROJ_N_PHASES = 6
+} wproj_phase;
+
+/*
+ * Per-phase timing with HIP events (the paper times its phases, e.g. "gridding" and
+ * "data loading", as averaged wall-clock, Section 3.2).  enable != 0 starts recording an
+ * event pair around every phase the handle's calls enqueue, on the call's stream;
+ * enable == 0 stops.  wproj_profile_read waits for the recorded events, writes the
+ * summed milliseconds and the number of recorded intervals of each phase into
+ * ms[WPROJ_N_PHASES] and count[WPROJ_N_PHASES] (host, either nullable), and clears the
+ * record.  Profiling mutates the handle: do not use it while other threads use the
+ * same handle.  Errors: WPROJ_EINVAL, WPROJ_EHIP.
+ */
+int wproj_profile(wproj_kernels *k, int enable);
+int wproj_profile_read(wproj_kernels *k, double *ms, int64_t *count);
+
 /* Message describing the last non-OK status returned on the calling thread ("" if none). */
 const char *wproj_last_error(void);
 

@@ -149,6 +149,12 @@ int validate(const wproj_params *p, std::vector<int32_t> &supp) {
 
 void destroy(wproj_kernels *k) {
   if (!k) return;
+  for (auto &v : k->prof)
+    for (auto &pr : v) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : k->event_pool) (void)hipEventDestroy(e);
   if (k->fft_fwd) rocfft_plan_destroy(k->fft_fwd);
   if (k->fft_inv) rocfft_plan_destroy(k->fft_inv);
   (void)hipFree(k->d_supp);
@@ -175,6 +181,17 @@ int check_device(const wproj_kernels *k) {
   if (dev != k->device)
     return fail(WPROJ_EINVAL, "handle was built on device %d but device %d is current", k->device, dev);
   return WPROJ_OK;
+}
+
+hipEvent_t take_event(wproj_kernels *k) {
+  if (!k->event_pool.empty()) {
+    hipEvent_t e = k->event_pool.back();
+    k->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
 }
 
 constexpr int64_t kAlign = 256;
@@ -227,7 +244,55 @@ int64_t workspace_bytes_for(const wproj_kernels *k, int64_t nvis) {
 
 }  // namespace
 
+namespace wproj {
+PhaseTimer::PhaseTimer(const wproj_kernels *kc, int ph, hipStream_t st)
+    : k(const_cast<wproj_kernels *>(kc)), phase(ph), s(st) {
+  if (!k->profiling) return;
+  hipEvent_t start = take_event(k);
+  stop = take_event(k);
+  if (!start || !stop || hipEventRecord(start, s) != hipSuccess) {
+    if (start) k->event_pool.push_back(start);
+    if (stop) k->event_pool.push_back(stop);
+    stop = nullptr;
+    return;
+  }
+  k->prof[phase].push_back({start, stop});
+}
+PhaseTimer::~PhaseTimer() {
+  if (stop) (void)hipEventRecord(stop, s);
+}
+}  // namespace wproj
+
 extern "C" {
+
+int wproj_profile(wproj_kernels *k, int enable) {
+  g_err.clear();
+  if (!k) return fail(WPROJ_EINVAL, "handle is NULL");
+  k->profiling = enable != 0;
+  return WPROJ_OK;
+}
+
+int wproj_profile_read(wproj_kernels *k, double *ms, int64_t *count) {
+  g_err.clear();
+  if (!k) return fail(WPROJ_EINVAL, "handle is NULL");
+  for (int p = 0; p < WPROJ_N_PHASES; ++p) {
+    double tot = 0.0;
+    for (auto &pr : k->prof[p]) {
+      HIP_TRY(hipEventSynchronize(pr.second));
+      float t = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&t, pr.first, pr.second));
+      tot += t;
+    }
+    if (ms) ms[p] = tot;
+    if (count) count[p] = (int64_t)k->prof[p].size();
+    for (auto &pr : k->prof[p]) {
+      k->event_pool.push_back(pr.first);
+      k->event_pool.push_back(pr.second);
+    }
+    k->prof[p].clear();
+  }
+  return WPROJ_OK;
+}
 
 const char *wproj_last_error(void) { return g_err.c_str(); }
 
@@ -422,6 +487,7 @@ int wproj_grid(const wproj_kernels *k, int64_t nvis, const double *uvw, const vo
   if (nvis == 0) return WPROJ_OK;
   hipStream_t s = (hipStream_t)stream;
   if (k->params.algorithm == WPROJ_ALGO_PLAIN) {
+    PhaseTimer pt(k, WPROJ_PHASE_PLAIN, s);
     HIP_TRY(launch_plain_grid(k, nvis, uvw, vis, weight, image_offsets, grid, weight_sum, counters, s));
     return WPROJ_OK;
   }
@@ -433,8 +499,14 @@ int wproj_grid(const wproj_kernels *k, int64_t nvis, const double *uvw, const vo
   const BinShape B = bin_shape(k);
   BinWorkspace W;
   carve(k, nvis, (char *)workspace, W);
-  HIP_TRY(launch_bin(k, B, nvis, uvw, vis, weight, image_offsets, weight_sum, counters, W, s));
-  HIP_TRY(launch_tiled_grid(k, B, W, grid, s));
+  {
+    PhaseTimer pt(k, WPROJ_PHASE_BIN, s);
+    HIP_TRY(launch_bin(k, B, nvis, uvw, vis, weight, image_offsets, weight_sum, counters, W, s));
+  }
+  {
+    PhaseTimer pt(k, WPROJ_PHASE_GRID, s);
+    HIP_TRY(launch_tiled_grid(k, B, W, grid, s));
+  }
   return WPROJ_OK;
 }
 
@@ -455,6 +527,7 @@ int wproj_degrid(const wproj_kernels *k, int64_t nvis, const double *uvw, const 
     return fail(WPROJ_EWORKSPACE, "workspace of %lld bytes given, %lld needed",
                 (long long)workspace_bytes, (long long)need);
   if (nvis == 0) return WPROJ_OK;
+  PhaseTimer pt(k, WPROJ_PHASE_DEGRID, (hipStream_t)stream);
   HIP_TRY(launch_plain_degrid(k, nvis, uvw, model_grid, image_offsets, vis_out, (hipStream_t)stream));
   return WPROJ_OK;
 }
@@ -485,13 +558,21 @@ int wproj_image(const wproj_kernels *k, int direction, void *grid, void *image,
   if (k->fft_work_bytes > 0) rocfft_execution_info_set_work_buffer(info, workspace, k->fft_work_bytes);
   void *buf[1] = {grid};
   if (direction == WPROJ_IMAGE_TO_GRID) {
-    HIP_TRY(launch_i2g_precorrect(k, image, grid, s));
+    {
+      PhaseTimer pt(k, WPROJ_PHASE_CORRECT, s);
+      HIP_TRY(launch_i2g_precorrect(k, image, grid, s));
+    }
+    PhaseTimer pt(k, WPROJ_PHASE_FFT, s);
     if (rocfft_execute(k->fft_fwd, buf, nullptr, info) != rocfft_status_success)
       return fail(WPROJ_EFFT, "rocfft_execute (forward) failed");
     return WPROJ_OK;
   }
-  if (rocfft_execute(k->fft_inv, buf, nullptr, info) != rocfft_status_success)
-    return fail(WPROJ_EFFT, "rocfft_execute (inverse) failed");
+  {
+    PhaseTimer pt(k, WPROJ_PHASE_FFT, s);
+    if (rocfft_execute(k->fft_inv, buf, nullptr, info) != rocfft_status_success)
+      return fail(WPROJ_EFFT, "rocfft_execute (inverse) failed");
+  }
+  PhaseTimer pt(k, WPROJ_PHASE_CORRECT, s);
   HIP_TRY(launch_g2i_correct(k, grid, image, direction == WPROJ_GRID_TO_IMAGE ? weight_sum : nullptr, s));
   return WPROJ_OK;
 }

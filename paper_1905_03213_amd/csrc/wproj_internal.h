@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "wproj.h"
@@ -126,7 +127,24 @@ struct wproj_kernels {
   int chunk = 8192;         // max records per gridder work item
   int n_cu = 256;           // compute units of the device
   size_t max_lds = 65536;   // LDS bytes available to one workgroup
+  // phase timing (wproj_profile): recorded (start, stop) event pairs per phase
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[WPROJ_N_PHASES];
+  std::vector<hipEvent_t> event_pool;
 };
+
+namespace wproj {
+// RAII marker: records a start event on construction and a stop event on destruction
+// when the handle is profiling.
+struct PhaseTimer {
+  wproj_kernels *k;
+  int phase;
+  hipStream_t s;
+  hipEvent_t stop = nullptr;
+  PhaseTimer(const wproj_kernels *kc, int ph, hipStream_t st);
+  ~PhaseTimer();
+};
+}  // namespace wproj
 
 namespace wproj {
 

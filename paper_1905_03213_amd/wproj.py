@@ -81,6 +81,20 @@ class Kernels:
                                                    None, _stream(stream)))
         return out
 
+    def profile(self, enable: bool = True):
+        """wproj_profile: record HIP events around each phase of this handle's calls."""
+        _lib.check("wproj_profile", _lib.lib().wproj_profile(self.handle, int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        """wproj_profile_read: {phase: (total_ms, n_intervals)} since the last read."""
+        import numpy as np
+
+        ms = np.zeros(len(_lib.PHASES), dtype=np.float64)
+        cnt = np.zeros(len(_lib.PHASES), dtype=np.int64)
+        _lib.check("wproj_profile_read", _lib.lib().wproj_profile_read(
+            self.handle, ms.ctypes.data_as(ctypes.c_void_p), cnt.ctypes.data_as(ctypes.c_void_p)))
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(_lib.PHASES)}
+
     def new_grid(self, device="cuda") -> torch.Tensor:
         n, ni = self.params["n"], self.params.get("n_images", 1)
         return torch.zeros((ni, n, n), dtype=self.cplx, device=device)

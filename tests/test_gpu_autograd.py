@@ -1,0 +1,103 @@
+"""The differentiable forward model on the GPU: prediction parity, chi^2 gradient parity
+with the oracle's adjoint, and finite differences through the GPU path itself."""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1905_03213_amd as W
+import synth
+from oracle import wproj_ref as R
+from paper_1905_03213_amd.autograd import chi2, predict
+
+from gpu_util import rel_max
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(prec, n=64):
+    wl = synth.cfg1w(n_w=9, s_max=10, n_vis=1500)
+    params = {**wl.params, "precision": prec, "algorithm": "tiled", "n": n}
+    plan = R.Plan(params)
+    rng = np.random.default_rng(21)
+    keep = R.snap(plan, wl.uvw, wl.weight)["valid"]
+    uvw = wl.uvw[keep]
+    img_true = np.zeros((n, n))
+    img_true[n // 2 + 5, n // 2 - 7] = 1.0
+    img_true[n // 2 - 9, n // 2 + 3] = 0.5
+    tabs = R.kernel_tables(plan)
+    v_obs = R.predict(plan, tabs, uvw, img_true) + 0.01 * (
+        rng.standard_normal(len(uvw)) + 1j * rng.standard_normal(len(uvw)))
+    wt = rng.uniform(0.5, 2.0, len(uvw))
+    return params, plan, tabs, uvw, v_obs, wt, rng
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-11), ("f32", 2e-5)])
+def test_prediction_and_chi2_gradient_match_oracle(prec, tol):
+    params, plan, tabs, uvw, v_obs, wt, rng = _problem(prec)
+    n = plan.n
+    cd = torch.complex128 if prec == "f64" else torch.complex64
+    rd = torch.float64 if prec == "f64" else torch.float32
+    # the model lives in the inner half of the field: at the edge the grid correction
+    # kappa(x) kappa(y) reaches ~1e6 and float32 rounding of kappa kappa I would dominate
+    img0 = np.zeros((n, n))
+    q = n // 4
+    img0[q:n - q, q:n - q] = 0.01 * rng.standard_normal((n - 2 * q, n - 2 * q))
+    img0 = img0.astype(np.float32 if prec != "f64" else np.float64)
+    k = W.make_kernels(params)
+    I = torch.tensor(img0, device="cuda", requires_grad=True)
+    U = torch.as_tensor(uvw).cuda()
+    Vo = torch.as_tensor(v_obs).to(cd).cuda()
+    Wt = torch.as_tensor(wt).to(rd).cuda()
+    pred = predict(I, k, U)
+    ref_pred = R.predict(plan, tabs, uvw, img0.astype(np.float64))
+    assert rel_max(pred.detach().to(torch.complex128).cpu().numpy(), ref_pred) <= tol
+    loss = chi2(I, k, U, Vo, Wt)
+    loss.backward()
+    ref_grad = R.chi2_grad(plan, tabs, uvw, Vo.to(torch.complex128).cpu().numpy(),
+                           Wt.double().cpu().numpy(), img0.astype(np.float64))[0]
+    got = I.grad.double().cpu().numpy()
+    # the gradient carries kappa(x) kappa(y) (up to ~1e6 on the edge pixels), which
+    # amplifies the transform's absolute rounding there: compare where kappa is moderate
+    inner = (slice(n // 4, n - n // 4), slice(n // 4, n - n // 4))
+    assert rel_max(got[inner], ref_grad[inner]) <= 10 * tol
+    if prec == "f64":
+        assert rel_max(got, ref_grad) <= 1e-9
+    k.free()
+
+
+def test_gradcheck_fp64_through_gpu_path():
+    params, plan, tabs, uvw, v_obs, wt, rng = _problem("f64", n=32)
+    params = {**params, "n": 32, "cell_rad": 2e-3}
+    plan = R.Plan(params)
+    keep = R.snap(plan, uvw, np.ones(len(uvw)))["valid"]
+    k = W.make_kernels(params)
+    U = torch.as_tensor(uvw[keep][:200]).cuda()
+    I = torch.tensor(0.01 * rng.standard_normal((32, 32)), device="cuda", requires_grad=True)
+    assert torch.autograd.gradcheck(lambda x: predict(x, k, U), (I,), eps=1e-6, atol=1e-7,
+                                    rtol=1e-5, fast_mode=True, nondet_tol=1e-12)
+    k.free()
+
+
+def test_chi2_finite_differences_fp64():
+    params, plan, tabs, uvw, v_obs, wt, rng = _problem("f64")
+    n = plan.n
+    k = W.make_kernels(params)
+    U = torch.as_tensor(uvw).cuda()
+    Vo = torch.as_tensor(v_obs).cuda()
+    Wt = torch.as_tensor(wt).cuda()
+    img0 = np.zeros((n, n))
+    q = n // 4
+    img0[q:n - q, q:n - q] = 0.01 * rng.standard_normal((n - 2 * q, n - 2 * q))
+    I = torch.tensor(img0, device="cuda", requires_grad=True)
+    chi2(I, k, U, Vo, Wt).backward()
+    g = I.grad.cpu().numpy()
+    for _ in range(20):
+        y, x = rng.integers(q, n - q, 2)
+        h = 1e-4
+        e = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        e[y, x] = h
+        with torch.no_grad():
+            fd = (chi2(I + e, k, U, Vo, Wt) - chi2(I - e, k, U, Vo, Wt)).item() / (2 * h)
+        assert abs(fd - g[y, x]) <= 1e-6 * max(1.0, np.abs(g).max())
+    k.free()
