@@ -82,7 +82,7 @@ typedef struct {
   int32_t precision;        /* wproj_precision */
   int32_t n_images;         /* >= 1: independent images gridded in one call (e.g. channels) */
   int32_t algorithm;        /* wproj_algorithm */
-  int32_t tile;             /* tiled gridder tile side: 0 = default, else 32, 64 or 128 */
+  int32_t tile;             /* tiled gridder tile side: 0 = default (16), else 16, 32 or 64 */
   int32_t reserved[5];      /* must be zero */
 } wproj_params;
 

@@ -133,8 +133,8 @@ int validate(const wproj_params *p, std::vector<int32_t> &supp) {
   if (p->n_images < 1) return fail(WPROJ_EINVAL, "n_images must be >= 1");
   if (p->algorithm != WPROJ_ALGO_TILED && p->algorithm != WPROJ_ALGO_PLAIN)
     return fail(WPROJ_EINVAL, "unknown algorithm %d", p->algorithm);
-  if (p->tile != 0 && p->tile != 32 && p->tile != 64 && p->tile != 128)
-    return fail(WPROJ_EINVAL, "tile must be 0, 32, 64 or 128");
+  if (p->tile != 0 && p->tile != 16 && p->tile != 32 && p->tile != 64)
+    return fail(WPROJ_EINVAL, "tile must be 0, 16, 32 or 64");
   for (int r : p->reserved)
     if (r != 0) return fail(WPROJ_EINVAL, "reserved fields must be zero");
   supp.assign(p->n_wplanes, p->support);
@@ -336,15 +336,14 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
   if (params->tile) {
     k->tile = params->tile;
     if (params->algorithm == WPROJ_ALGO_TILED && tile_shape(k, k->tile).lds_bytes + 256 > k->max_lds)
-      return fail(WPROJ_EUNSUPPORTED, "tile %d with support %d needs %zu bytes of LDS, %zu available",
-                  k->tile, k->s_max, tile_shape(k, k->tile).lds_bytes, k->max_lds);
+      return fail(WPROJ_EUNSUPPORTED, "tile %d with support %d needs %zu bytes of LDS per wavefront",
+                  k->tile, k->s_max, tile_shape(k, k->tile).lds_bytes);
   } else {
-    k->tile = 64;
-    while (k->tile > 16 && tile_shape(k, k->tile).lds_bytes + 256 > k->max_lds) k->tile /= 2;
+    k->tile = 16;
   }
   {
     const int64_t nt = (params->n + k->tile - 1) / k->tile;
-    k->plane_in_key = (int64_t)params->n_images * nt * nt * params->n_wplanes <= (1ll << 24);
+    k->plane_in_key = (int64_t)params->n_images * nt * nt * params->n_wplanes <= (1ll << 25);
   }
 
   Geometry &G = k->geo;

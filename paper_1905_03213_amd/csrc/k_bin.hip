@@ -24,22 +24,25 @@ __device__ inline uint64_t lane_mask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Wave-aggregated atomicAdd(count[key], 1): returns this lane's slot.  Lanes with
-// key == kInvalid take no part.
+// atomicAdd(count[key], 1) for every lane with a key, returning the lane's slot.  All lanes
+// issue one atomic instruction together (one memory round trip per wave); the largest
+// group of lanes sharing the first active lane's key is folded into a single add by
+// that lane, which covers the common case of neighbouring rows landing in one bin.
+// Lanes with key == kInvalid take no part.
 __device__ inline uint32_t aggregated_slot(uint32_t *count, uint32_t key) {
-  uint64_t pending = __ballot(key != kInvalid);
-  uint32_t slot = 0;
-  while (pending) {
-    const int leader = __ffsll((unsigned long long)pending) - 1;
-    const uint32_t lk = __shfl(key, leader, 64);
-    const uint64_t same = __ballot(key == lk) & pending;
-    uint32_t base = 0;
-    if ((threadIdx.x & 63) == leader) base = atomicAdd(&count[lk], (uint32_t)__popcll(same));
-    base = __shfl(base, leader, 64);
-    if (key == lk) slot = base + (uint32_t)__popcll(same & lane_mask_lt());
-    pending &= ~same;
-  }
-  return slot;
+  const int lane = threadIdx.x & 63;
+  const uint64_t active = __ballot(key != kInvalid);
+  if (active == 0) return 0;
+  const int leader = __ffsll((unsigned long long)active) - 1;
+  const uint32_t lk = __shfl(key, leader, 64);
+  const uint64_t same = __ballot(key == lk) & active;
+  uint32_t inc = 0;
+  if (key != kInvalid) inc = (key == lk) ? (lane == leader ? (uint32_t)__popcll(same) : 0u) : 1u;
+  uint32_t got = 0;
+  if (inc) got = atomicAdd(&count[key], inc);
+  const uint32_t base = __shfl(got, leader, 64);
+  if (key == lk) return base + (uint32_t)__popcll(same & lane_mask_lt());
+  return got;
 }
 
 __device__ inline double wave_sum(double v) {

@@ -1,21 +1,25 @@
-// Tiled gridder: each work item is a run of binned records of one uv-tile; its
-// workgroup accumulates them in an LDS copy of the tile plus an (S_max - 1)-cell halo
-// on the high-x / high-y sides, then adds the non-zero cells to the grid in HBM with
-// global atomics.  Most of the read-modify-write traffic of gridding therefore stays
-// in LDS instead of going to HBM (the paper's CUDA gridder writes every tap of every
-// visibility to global memory atomically, Section 2.2).
+// Tiled gridder: each work item is a run of binned records of one uv-tile.  One
+// wavefront owns the work item and accumulates its records in a private LDS copy of
+// the tile plus an (S_max - 1)-cell halo on the high-x / high-y sides, then adds the
+// non-zero cells to the grid in HBM with global atomics.  Most of the read-modify-write
+// traffic of gridding therefore stays in LDS instead of going to HBM (the paper's CUDA
+// gridder writes every tap of every visibility to global memory atomically, Section 2.2).
 //
-// Launch is persistent: one wave of workgroups sized to fill every CU pulls work items
-// from a queue head in HBM until the queue is empty, which evens out the very uneven
-// per-tile visibility counts of Earth-rotation tracks.
+// Because the tile is private to one wavefront and its 64 lanes always touch 64
+// distinct cells of a record's footprint, the accumulation is a plain LDS read, add and
+// write: instructions of one wavefront reach LDS in order, so a later record sees the
+// earlier record's update without atomics.  (LDS floating-point atomics on this chip
+// retire at only a few lanes per clock; plain 64-bit reads and writes run at full
+// LDS bandwidth.)  Tiles are small (16 or 32 cells) so that a CU holds many wavefronts,
+// each with its own tile, to hide LDS and memory latency.
 //
-// Inside a workgroup each wavefront takes 64 consecutive records with one coalesced
-// load, then walks them one at a time, broadcasting each record's fields from its
-// owning lane (readlane); the 64 lanes cover the S x S taps of the record: lane t loads
-// tap t of the sub-kernel (one coalesced 8-byte load per lane) and adds
-// W V C into LDS at (y0 + kv, x0 + ku).  The LDS tile is stored as separate real and
-// imaginary planes with a row pitch chosen so that the rows of a footprint land in
-// different banks.
+// Launch is persistent: enough wavefronts to fill every CU pull work items from a queue
+// head in HBM until the queue is empty, which evens out the very uneven per-tile
+// visibility counts of Earth-rotation tracks.  Records are read with wave-uniform
+// (scalar) loads in groups of kGroup, and the groups' kernel-table loads are issued
+// together, lane t loading tap t of the record's sub-kernel.
+#include <algorithm>
+
 #include "wproj_tiled.h"
 
 namespace wproj {
@@ -41,142 +45,182 @@ __device__ inline double bcast(double v, int j) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-template <typename Real, typename Rec, typename Tab, int S, int BS>
-__global__ void __launch_bounds__(BS)
-    tiled_grid_kernel(Geometry G, BinShape B, int pitch, int rows, const Tab *__restrict__ tab,
-                      const Rec *__restrict__ rec, const WorkItem *__restrict__ items,
-                      const uint32_t *__restrict__ n_items_ptr, uint32_t *counter, Real *grid) {
+template <typename Real> struct Cx;
+template <> struct Cx<float> { using T = float2; };
+template <> struct Cx<double> { using T = double2; };
+
+// Records processed per batch by one wavefront: their table loads are all issued
+// before the first is consumed, so up to kGroup memory latencies overlap per wave.
+constexpr int kGroup = 8;
+constexpr int kMaxWavesPerBlock = 4;
+
+template <typename Real, typename Rec, typename Tab, int S>
+__global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
+    tiled_grid_kernel(Geometry G, BinShape B, int pitch, int rows, int wave_lds,
+                      const Tab *__restrict__ tab, const Rec *__restrict__ rec,
+                      const WorkItem *__restrict__ items, const uint32_t *__restrict__ n_items_ptr,
+                      uint32_t *counter, Real *grid) {
+  using C2 = typename Cx<Real>::T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  Real *sre = reinterpret_cast<Real *>(smem_raw);
-  const int plane = rows * pitch;
-  Real *sim = sre + plane;
-  __shared__ uint32_t s_item;
-  constexpr int NW = BS / 64;
-  const uint32_t n_items = *n_items_ptr;
   const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  C2 *acc = reinterpret_cast<C2 *>(smem_raw) + (size_t)wid * wave_lds;
+  const uint32_t n_items = *n_items_ptr;
   const int64_t cells = (int64_t)G.n * G.n;
   const int tiles_per_img = B.ntx * B.nty;
-  // fixed-support lanes: tap (kv, ku) of lane t = kv S + ku
-  const int lane_kv = S > 0 ? lane / (S > 0 ? S : 1) : 0;
-  const int lane_ku = S > 0 ? lane - lane_kv * S : 0;
+  const int area = rows * pitch;
+  // fixed support: lane t holds tap (kv, ku) = (t / S, t % S) at offset kv pitch + ku
+  const int lane_off = S > 0 ? (lane / (S > 0 ? S : 1)) * pitch + lane % (S > 0 ? S : 1) : 0;
+  const bool lane_on = S > 0 ? lane < S * S : true;
 
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
-    __syncthreads();
-    const uint32_t it = s_item;
+    uint32_t got = 0;
+    if (lane == 0) got = atomicAdd(counter, 1u);
+    const uint32_t it = (uint32_t)__builtin_amdgcn_readlane((int)got, 0);
     if (it >= n_items) break;
     const WorkItem w = items[it];
     const int img = (int)(w.tile / (uint32_t)tiles_per_img);
     const int rt = (int)(w.tile - (uint32_t)img * tiles_per_img);
     const int ty = rt / B.ntx, tx = rt - ty * B.ntx;
     const int ox = tx * B.tile, oy = ty * B.tile;
-    for (int i = threadIdx.x; i < 2 * plane; i += BS) sre[i] = Real(0);
-    __syncthreads();
+    for (int i = lane; i < area; i += 64) acc[i] = C2{Real(0), Real(0)};
 
-    for (uint32_t r0 = w.begin + (uint32_t)wid * 64u; r0 < w.end; r0 += NW * 64u) {
-      Rec mine;
-      if (r0 + lane < w.end) {
-        mine = rec[r0 + lane];
-      } else {
-        mine.xy = 0;
-        mine.tap = 0;
-        mine.wr = Real(0);
-        mine.wi = Real(0);
-      }
-      const int cnt = (int)min(64u, w.end - r0);
-      for (int j = 0; j < cnt; ++j) {
-        const uint32_t xy = bcast(mine.xy, j);
-        const uint32_t tp = bcast(mine.tap, j);
-        const Real wr = bcast(mine.wr, j);
-        const Real wi = bcast(mine.wi, j);
-        const int lx = (int)(xy & 0xffffu) - ox;
-        const int ly = (int)(xy >> 16) - oy;
-        const uint32_t tb = tp & kTapMask;
-        const int base = ly * pitch + lx;
-        if (S > 0 && S * S <= 64) {
-          if (lane < S * S) {
-            const auto c = tab_load(tab, tb + lane);
-            const Real gr = wr * c.x - wi * c.y;
-            const Real gi = wr * c.y + wi * c.x;
-            const int a = base + lane_kv * pitch + lane_ku;
-            atomicAdd(&sre[a], gr);
-            atomicAdd(&sim[a], gi);
-          }
+    if (S > 0 && S * S <= 64) {
+      // Fast path (fixed support, one tap per lane).  Records arrive 64 at a time with
+      // one coalesced load (lane i holds record b + i) and are broadcast with readlane;
+      // the next batch is loaded while this one is processed.  Table taps are loaded one
+      // group of kGroup records ahead of their use.
+      const uint32_t n_rec = w.end - w.begin;
+      auto load_batch = [&](uint32_t b, Rec &dst) {
+        const uint32_t i = b + (uint32_t)lane;
+        if (i < n_rec) {
+          dst = rec[w.begin + i];
         } else {
-          const int Sr = S > 0 ? S : (int)(tp >> kTapBits) + 1;
-          for (int t = lane; t < Sr * Sr; t += 64) {
-            const int kv = t / Sr, ku = t - kv * Sr;
-            const auto c = tab_load(tab, tb + t);
-            const Real gr = wr * c.x - wi * c.y;
-            const Real gi = wr * c.y + wi * c.x;
-            const int a = base + kv * pitch + ku;
-            atomicAdd(&sre[a], gr);
-            atomicAdd(&sim[a], gi);
+          dst.xy = (uint32_t)ox | ((uint32_t)oy << 16);
+          dst.tap = 0;
+          dst.wr = Real(0);
+          dst.wi = Real(0);
+        }
+      };
+      const uint32_t tap_lane = lane_on ? (uint32_t)lane : 0u;
+      using Tap = decltype(tab_load(tab, 0u));
+      constexpr int kGroups = 64 / kGroup;
+      Rec cur;
+      load_batch(0, cur);
+      for (uint32_t b = 0; b < n_rec; b += 64) {
+        Rec nxt;
+        const bool more = b + 64 < n_rec;
+        if (more) load_batch(b + 64, nxt);
+        // straight-line pipeline over the batch's 8 groups (padding records of a partial
+        // batch carry zero weight): group g+1's taps load while group g accumulates
+        Tap c[2][kGroup];
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) c[0][i] = tab_load(tab, (bcast(cur.tap, i) & kTapMask) + tap_lane);
+#pragma unroll
+        for (int gI = 0; gI < kGroups; ++gI) {
+          if (gI + 1 < kGroups) {
+#pragma unroll
+            for (int i = 0; i < kGroup; ++i)
+              c[(gI + 1) & 1][i] =
+                  tab_load(tab, (bcast(cur.tap, (gI + 1) * kGroup + i) & kTapMask) + tap_lane);
+          }
+#pragma unroll
+          for (int i = 0; i < kGroup; ++i) {
+            const int j = gI * kGroup + i;
+            const uint32_t xy = bcast(cur.xy, j);
+            const Real wr = bcast(cur.wr, j), wi = bcast(cur.wi, j);
+            const int base = ((int)(xy >> 16) - oy) * pitch + ((int)(xy & 0xffffu) - ox);
+            if (lane_on) {
+              C2 a = acc[base + lane_off];
+              a.x += wr * c[gI & 1][i].x - wi * c[gI & 1][i].y;
+              a.y += wr * c[gI & 1][i].y + wi * c[gI & 1][i].x;
+              acc[base + lane_off] = a;
+            }
           }
         }
+        if (more) cur = nxt;
       }
-    }
-    __syncthreads();
-
-    Real *g = grid + 2 * cells * img;
-    for (int i = threadIdx.x; i < plane; i += BS) {
-      const Real vr = sre[i], vi = sim[i];
-      if (vr != Real(0) || vi != Real(0)) {
-        const int ry = i / pitch, rx = i - ry * pitch;
-        const int gx = ox + rx, gy = oy + ry;
-        if (rx < rows && gx < G.n && gy < G.n) {
-          const int64_t c = (int64_t)gy * G.n + gx;
-          unsafeAtomicAdd(&g[2 * c], vr);
-          unsafeAtomicAdd(&g[2 * c + 1], vi);
+    } else {
+      // General path (per-record support up to 32): records by wave-uniform loads, each
+      // record's taps in passes of 64 lanes.
+      for (uint32_t r = w.begin; r < w.end; ++r) {
+        const Rec rr = rec[r];
+        const uint32_t tp = rr.tap;
+        const int Sr = S > 0 ? S : (int)(tp >> kTapBits) + 1;
+        const uint32_t tb = tp & kTapMask;
+        const int base = ((int)(rr.xy >> 16) - oy) * pitch + ((int)(rr.xy & 0xffffu) - ox);
+        for (int t = lane; t < Sr * Sr; t += 64) {
+          const int kv = t / Sr, ku = t - kv * Sr;
+          const auto c = tab_load(tab, tb + t);
+          C2 a = acc[base + kv * pitch + ku];
+          a.x += rr.wr * c.x - rr.wi * c.y;
+          a.y += rr.wr * c.y + rr.wi * c.x;
+          acc[base + kv * pitch + ku] = a;
         }
       }
     }
-    __syncthreads();
+
+    // flush the tile (with halo) to the grid
+    Real *g = grid + 2 * cells * img;
+    for (int i = lane; i < rows * rows; i += 64) {
+      const int ry = i / rows, rx = i - ry * rows;
+      const int gy = oy + ry, gx = ox + rx;
+      const C2 v = acc[ry * pitch + rx];
+      if (gx < G.n && gy < G.n && (v.x != Real(0) || v.y != Real(0))) {
+        const int64_t c = (int64_t)gy * G.n + gx;
+        unsafeAtomicAdd(&g[2 * c], v.x);
+        unsafeAtomicAdd(&g[2 * c + 1], v.y);
+      }
+    }
   }
 }
 
-template <typename Real, typename Rec, typename Tab, int S, int BS>
+template <typename Real, typename Rec, typename Tab, int S>
 hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
                       const BinWorkspace &W, void *grid, hipStream_t s) {
-  auto kern = tiled_grid_kernel<Real, Rec, Tab, S, BS>;
+  auto kern = tiled_grid_kernel<Real, Rec, Tab, S>;
+  // as many wavefronts per workgroup (up to 4) as their private tiles fit in LDS
+  const int wpb = (int)std::max<size_t>(1, std::min<size_t>(kMaxWavesPerBlock, k->max_lds / ts.lds_bytes));
+  const size_t lds = ts.lds_bytes * wpb;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)ts.lds_bytes);
+                                     (int)lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BS, ts.lds_bytes);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb, lds);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   const unsigned blocks = (unsigned)(k->n_cu * per_cu);
-  hipLaunchKernelGGL(kern, dim3(blocks), dim3(BS), ts.lds_bytes, s, k->geo, B, ts.pitch, ts.rows,
-                     (const Tab *)k->d_tab, (const Rec *)W.rec, W.items, W.choff + B.n_tiles,
-                     W.counter, (Real *)grid);
+  const int wave_lds = (int)(ts.lds_bytes / (2 * sizeof(Real)));
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, s, k->geo, B, ts.pitch,
+                     ts.rows, wave_lds, (const Tab *)k->d_tab, (const Rec *)W.rec, W.items,
+                     W.choff + B.n_tiles, W.counter, (Real *)grid);
   return hipGetLastError();
 }
 
 template <typename Real, typename Rec, typename Tab>
 hipError_t dispatch_support(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
                             const BinWorkspace &W, void *grid, hipStream_t s) {
-  constexpr int BS = 512;
   if (k->uniform_support && k->s_max == 8)
-    return launch_one<Real, Rec, Tab, 8, BS>(k, B, ts, W, grid, s);
+    return launch_one<Real, Rec, Tab, 8>(k, B, ts, W, grid, s);
   if (k->uniform_support && k->s_max == 7)
-    return launch_one<Real, Rec, Tab, 7, BS>(k, B, ts, W, grid, s);
-  return launch_one<Real, Rec, Tab, 0, BS>(k, B, ts, W, grid, s);
+    return launch_one<Real, Rec, Tab, 7>(k, B, ts, W, grid, s);
+  return launch_one<Real, Rec, Tab, 0>(k, B, ts, W, grid, s);
 }
 
 }  // namespace
 
 TileShape tile_shape(const wproj_kernels *k, int tile) {
+  // One wavefront's private tile: rows = T + S_max - 1 complex cells per side.  The row
+  // pitch (in complex cells) is odd-multiple-of-8 so that the 4 rows of 8 taps a half
+  // wavefront touches fall on different LDS banks for 64-bit accesses.
   TileShape t;
   t.tile = tile;
   t.rows = tile + k->s_max - 1;
-  const int sref = k->uniform_support ? (k->s_max & 31) : 16;
   int pitch = t.rows;
-  while ((pitch & 31) != sref) ++pitch;
+  while ((pitch & 15) != 8) ++pitch;
   t.pitch = pitch;
   const size_t real = k->params.precision == WPROJ_F64 ? 8 : 4;
-  t.lds_bytes = 2 * (size_t)t.rows * t.pitch * real;
+  t.lds_bytes = 2 * (size_t)t.rows * t.pitch * real;  // per wavefront
   return t;
 }
 

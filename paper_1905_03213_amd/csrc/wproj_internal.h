@@ -122,9 +122,9 @@ struct wproj_kernels {
   double *d_taper = nullptr;
   rocfft_plan fft_fwd = nullptr, fft_inv = nullptr;
   size_t fft_work_bytes = 0;
-  int tile = 64;            // tiled gridder tile side
+  int tile = 16;            // tiled gridder tile side
   bool plane_in_key = true; // bin by (tile, plane) rather than tile alone
-  int chunk = 8192;         // max records per gridder work item
+  int chunk = 2048;         // max records per gridder work item
   int n_cu = 256;           // compute units of the device
   size_t max_lds = 65536;   // LDS bytes available to one workgroup
   // phase timing (wproj_profile): recorded (start, stop) event pairs per phase
