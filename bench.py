@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the step replayed from a captured HIP graph")
     return ap.parse_args()
 
 
@@ -86,6 +88,9 @@ def main():
     cnt = torch.zeros(3, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
 
+    tile, chunk = W.autotune(k, uvw, vis32, wt32, workspace=ws)
+    log(f"autotuned: tile {tile}, chunk {chunk}")
+
     def step():
         g.zero_()
         sw.zero_()
@@ -112,6 +117,29 @@ def main():
     k.profile(False)
     ms_step = ms_total / args.steps
     value = n_valid / (ms_step * 1e-3) / 1e6
+
+    # the same step captured once in a HIP graph and replayed (launch overhead removed)
+    graph_ms = None
+    if args.graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            step()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            graph.replay()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        graph_ms = ev0.elapsed_time(ev1) / args.steps
+        del graph
     per = {name: ms / max(c, 1) for name, (ms, c) in phases.items() if c}
     log(f"fp32 tiled: {ms_step:.3f} ms/step, {value:.1f} Mvis/s, phases {per}")
 
@@ -147,6 +175,8 @@ def main():
     degrid_ms = dph["degrid"][0] / max(dph["degrid"][1], 1)
 
     extra = {"phases_ms": per, "degrid": {"ms": degrid_ms, "mvis_per_s": n_valid / degrid_ms / 1e3},
+             "tuning": {"tile": tile, "chunk": chunk},
+             "graph_replay_ms_per_step": graph_ms,
              "counters": {"dropped": counters[0], "w_clamped": counters[1], "bad_weight": counters[2]},
              "nvis_total": nvis, "nvis_gridded": n_valid}
     del ws
@@ -200,7 +230,7 @@ def main():
                                "27-antenna 8 h track at 10 s, 64 channels 1.0-1.5 GHz "
                                f"({nvis} visibilities), 128 w-planes, S=8, oversampling 8",
                    "n": n, "nvis": nvis, "n_wplanes": 128, "support": 8, "oversample": 8,
-                   "kernel_image_size": params["kernel_image_size"], "tile": 64,
+                   "kernel_image_size": params["kernel_image_size"], "tile": tile, "chunk": chunk,
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

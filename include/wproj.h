@@ -186,6 +186,28 @@ typedef enum {
 int wproj_image(const wproj_kernels *k, int direction, void *grid, void *image,
                 const double *weight_sum, void *workspace, int64_t workspace_bytes, void *stream);
 
+/*
+ * Choose the tiled gridder's tile side (16 or 32 cells) and work-item length (512 ..
+ * 8192 binned records) for this handle by timing each candidate on the caller's data
+ * (one warm-up and one timed wproj_grid per candidate, HIP events on `stream`), then keep
+ * the fastest in the handle.  The choice is also cached per problem shape (grid size,
+ * images, planes, supports, oversampling, precision, visibility count rounded to a
+ * power of two) for the life of the process, and later calls on a handle of the same
+ * shape reuse it without timing.  Arguments are those of wproj_grid; scratch_grid
+ * ([n_images][n][n], device) is written with garbage.  Synchronises `stream`.  Mutates
+ * the handle: no other call may use it concurrently.  The paper attributes the
+ * flattening of its scaling curves to workload imbalance between threads and nodes
+ * (Sections 3.2, 4); the work-item length is the knob that trades that imbalance
+ * against per-item overhead.  Errors: as wproj_grid; WPROJ_EUNSUPPORTED for a handle
+ * built with WPROJ_ALGO_PLAIN.
+ */
+int wproj_autotune(wproj_kernels *k, int64_t nvis, const double *uvw, const void *vis,
+                   const void *weight, const int64_t *image_offsets, void *scratch_grid,
+                   void *workspace, int64_t workspace_bytes, void *stream);
+
+/* The tiled gridder configuration in use: *tile (cells) and *chunk (records), host. */
+int wproj_tuning(const wproj_kernels *k, int32_t *tile, int32_t *chunk);
+
 /* Phases timed by wproj_profile. */
 typedef enum {
   WPROJ_PHASE_BIN = 0,      /* key/count, scan, scatter, work list (tiled gridding) */

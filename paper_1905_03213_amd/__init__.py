@@ -15,6 +15,7 @@ from .wproj import (  # noqa: F401
     IMAGE_TO_GRID,
     Kernels,
     WprojError,
+    autotune,
     degrid,
     grid,
     image,

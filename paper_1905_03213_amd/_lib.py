@@ -19,8 +19,8 @@ STATUS = {0: "WPROJ_OK", -1: "WPROJ_EINVAL", -2: "WPROJ_ENOMEM", -3: "WPROJ_EHIP
           -4: "WPROJ_EUNSUPPORTED", -5: "WPROJ_EWORKSPACE", -6: "WPROJ_EFFT"}
 
 EXPORTED = ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_workspace_size",
-            "wproj_grid", "wproj_degrid", "wproj_image", "wproj_profile", "wproj_profile_read",
-            "wproj_last_error", "wproj_version")
+            "wproj_grid", "wproj_degrid", "wproj_image", "wproj_autotune", "wproj_tuning",
+            "wproj_profile", "wproj_profile_read", "wproj_last_error", "wproj_version")
 PHASES = ("bin", "grid", "plain", "fft", "correct", "degrid")
 
 
@@ -69,14 +69,16 @@ def lib():
     L.wproj_grid.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
     L.wproj_degrid.argtypes = [vp, i64, vp, vp, vp, vp, vp, i64, vp]
     L.wproj_image.argtypes = [vp, i32, vp, vp, vp, vp, i64, vp]
+    L.wproj_autotune.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, i64, vp]
+    L.wproj_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     L.wproj_profile.argtypes = [vp, i32]
     L.wproj_profile_read.argtypes = [vp, vp, vp]
     L.wproj_last_error.restype = ctypes.c_char_p
     L.wproj_last_error.argtypes = []
     L.wproj_version.argtypes = []
     for name in ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_grid",
-                 "wproj_degrid", "wproj_image", "wproj_profile", "wproj_profile_read",
-                 "wproj_version"):
+                 "wproj_degrid", "wproj_image", "wproj_autotune", "wproj_tuning", "wproj_profile",
+                 "wproj_profile_read", "wproj_version"):
         getattr(L, name).restype = i32
     _lib = L
     return L

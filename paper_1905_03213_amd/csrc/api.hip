@@ -6,8 +6,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <new>
+#include <tuple>
 
 #include "wproj_tiled.h"
 
@@ -233,14 +235,43 @@ int64_t carve(const wproj_kernels *k, int64_t nvis, char *base, BinWorkspace &W)
   return off;
 }
 
+constexpr int kTuneTiles[] = {16, 32};
+constexpr int kTuneChunks[] = {512, 1024, 2048, 4096, 8192};
+
+bool plane_in_key_for(const wproj_kernels *k, int tile) {
+  const int64_t nt = (k->params.n + tile - 1) / tile;
+  return (int64_t)k->params.n_images * nt * nt * k->params.n_wplanes <= (1ll << 25);
+}
+
+// Workspace for nvis visibilities under any tile/chunk the autotuner may select.
 int64_t workspace_bytes_for(const wproj_kernels *k, int64_t nvis) {
   int64_t ws = align_up((int64_t)k->fft_work_bytes);
   if (k->params.algorithm == WPROJ_ALGO_TILED) {
+    wproj_kernels tmp;  // geometry only
+    tmp.params = k->params;
+    for (int tile : kTuneTiles) {
+      tmp.tile = tile;
+      tmp.plane_in_key = plane_in_key_for(k, tile);
+      tmp.chunk = kTuneChunks[0];
+      BinWorkspace W;
+      ws = std::max(ws, carve(&tmp, nvis, nullptr, W));
+    }
     BinWorkspace W;
     ws = std::max(ws, carve(k, nvis, nullptr, W));
   }
   return ws;
 }
+
+struct TuneKey {
+  int n, n_images, n_w, s_max, uniform, O, precision;
+  int log2_nvis;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(n, n_images, n_w, s_max, uniform, O, precision, log2_nvis) <
+           std::tie(o.n, o.n_images, o.n_w, o.s_max, o.uniform, o.O, o.precision, o.log2_nvis);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;
 
 }  // namespace
 
@@ -341,10 +372,7 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
   } else {
     k->tile = 16;
   }
-  {
-    const int64_t nt = (params->n + k->tile - 1) / k->tile;
-    k->plane_in_key = (int64_t)params->n_images * nt * nt * params->n_wplanes <= (1ll << 25);
-  }
+  k->plane_in_key = plane_in_key_for(k, k->tile);
 
   Geometry &G = k->geo;
   G.n = n;
@@ -506,6 +534,91 @@ int wproj_grid(const wproj_kernels *k, int64_t nvis, const double *uvw, const vo
     PhaseTimer pt(k, WPROJ_PHASE_GRID, s);
     HIP_TRY(launch_tiled_grid(k, B, W, grid, s));
   }
+  return WPROJ_OK;
+}
+
+int wproj_tuning(const wproj_kernels *k, int32_t *tile, int32_t *chunk) {
+  g_err.clear();
+  if (!k) return fail(WPROJ_EINVAL, "handle is NULL");
+  if (tile) *tile = k->tile;
+  if (chunk) *chunk = k->chunk;
+  return WPROJ_OK;
+}
+
+int wproj_autotune(wproj_kernels *k, int64_t nvis, const double *uvw, const void *vis,
+                   const void *weight, const int64_t *image_offsets, void *scratch_grid,
+                   void *workspace, int64_t workspace_bytes, void *stream) {
+  g_err.clear();
+  if (!k) return fail(WPROJ_EINVAL, "handle is NULL");
+  if (k->params.algorithm != WPROJ_ALGO_TILED)
+    return fail(WPROJ_EUNSUPPORTED, "autotuning applies to the tiled gridder only");
+  int lg = 0;
+  while (lg < 62 && (1ll << (lg + 1)) <= std::max<int64_t>(nvis, 1)) ++lg;
+  const TuneKey key{k->params.n, k->params.n_images, k->params.n_wplanes, k->s_max,
+                    k->uniform_support ? 1 : 0, k->params.oversample, k->params.precision, lg};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      k->tile = it->second.first;
+      k->chunk = it->second.second;
+      k->plane_in_key = plane_in_key_for(k, k->tile);
+      return WPROJ_OK;
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } eg{e0, e1};
+  const bool was_profiling = k->profiling;
+  k->profiling = false;
+  const int tile0 = k->tile, chunk0 = k->chunk;
+  float best = -1.0f;
+  int best_tile = tile0, best_chunk = chunk0;
+  for (int tile : kTuneTiles) {
+    if (tile_shape(k, tile).lds_bytes + 256 > k->max_lds) continue;
+    for (int chunk : kTuneChunks) {
+      k->tile = tile;
+      k->chunk = chunk;
+      k->plane_in_key = plane_in_key_for(k, tile);
+      int rc = wproj_grid(k, nvis, uvw, vis, weight, image_offsets, scratch_grid, nullptr, nullptr,
+                          workspace, workspace_bytes, stream);
+      if (rc == WPROJ_OK) {
+        HIP_TRY(hipEventRecord(e0, s));
+        rc = wproj_grid(k, nvis, uvw, vis, weight, image_offsets, scratch_grid, nullptr, nullptr,
+                        workspace, workspace_bytes, stream);
+        HIP_TRY(hipEventRecord(e1, s));
+      }
+      if (rc != WPROJ_OK) {
+        k->tile = tile0;
+        k->chunk = chunk0;
+        k->plane_in_key = plane_in_key_for(k, tile0);
+        k->profiling = was_profiling;
+        return rc;
+      }
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (best < 0.0f || ms < best) {
+        best = ms;
+        best_tile = tile;
+        best_chunk = chunk;
+      }
+    }
+  }
+  k->tile = best_tile;
+  k->chunk = best_chunk;
+  k->plane_in_key = plane_in_key_for(k, best_tile);
+  k->profiling = was_profiling;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = {best_tile, best_chunk};
   return WPROJ_OK;
 }
 

@@ -75,6 +75,12 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Degridding: 8 visibilities per wavefront pass, a group of 8 lanes per visibility.
+// Lane r of a group takes footprint rows kv = r, r + 8, ... and walks each row's taps:
+// the row's S taps are contiguous in the sub-kernel and the row's S cells contiguous in
+// the grid, so a group reads whole 64-byte runs.  The 8 partial sums of a visibility are
+// combined with three butterfly shuffles inside the group.  Each lane works out its own
+// visibility's footprint (the same FP64 rule as gridding).
 template <typename Real, typename Cplx, typename Tab>
 __global__ void __launch_bounds__(256)
     plain_degrid_kernel(Geometry G, const Tab *__restrict__ tab, int64_t nvis,
@@ -82,31 +88,40 @@ __global__ void __launch_bounds__(256)
                         const int64_t *__restrict__ img_off, Cplx *__restrict__ out,
                         int64_t per_wave) {
   const int lane = threadIdx.x & 63;
+  const int grp = lane >> 3, r = lane & 7;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t j0 = wave * per_wave;
   const int64_t j1 = min(nvis, j0 + per_wave);
   const int64_t cells = (int64_t)G.n * G.n;
-  for (int64_t j = j0; j < j1; ++j) {
-    const int img = image_of(img_off, G.n_images, j);
-    Footprint f;
+  for (int64_t jb = j0; jb < j1; jb += 8) {
+    const int64_t j = jb + grp;
     Real re = 0, im = 0;
-    if (img >= 0 && classify(G, uvw + 3 * j, 1.0, f) == kGridded) {
-      const int S = G.supp[f.p];
-      const Tab *T = tab + G.tab_off[f.p] + ((int64_t)f.ov * G.O + f.ou) * S * S;
-      const Cplx *gimg = grid + cells * img;
-      for (int t = lane; t < S * S; t += 64) {
-        const int kv = t / S, ku = t - kv * S;
-        const auto k = load_tap(T, t);
-        const Cplx m = gimg[(int64_t)(f.y0 + kv) * G.n + (f.x0 + ku)];
-        re += k.x * m.x + k.y * m.y;  // conj(k) * m
-        im += k.x * m.y - k.y * m.x;
+    if (j < j1) {
+      const int img = image_of(img_off, G.n_images, j);
+      Footprint f;
+      if (img >= 0 && classify(G, uvw + 3 * j, 1.0, f) == kGridded) {
+        const int S = G.supp[f.p];
+        const Tab *T = tab + G.tab_off[f.p] + ((int64_t)f.ov * G.O + f.ou) * S * S;
+        const Cplx *gimg = grid + cells * img;
+        for (int kv = r; kv < S; kv += 8) {
+          const Tab *trow = T + kv * S;
+          const Cplx *grow = gimg + (int64_t)(f.y0 + kv) * G.n + f.x0;
+          for (int ku = 0; ku < S; ++ku) {
+            const auto k = load_tap(trow, ku);
+            const Cplx m = grow[ku];
+            re += k.x * m.x + k.y * m.y;  // conj(k) * m
+            im += k.x * m.y - k.y * m.x;
+          }
+        }
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      re += __shfl_xor(re, off, 64);
-      im += __shfl_xor(im, off, 64);
-    }
-    if (lane == 0) {
+    re += __shfl_xor(re, 1, 64);
+    im += __shfl_xor(im, 1, 64);
+    re += __shfl_xor(re, 2, 64);
+    im += __shfl_xor(im, 2, 64);
+    re += __shfl_xor(re, 4, 64);
+    im += __shfl_xor(im, 4, 64);
+    if (r == 0 && j < j1) {
       Cplx o;
       o.x = re;
       o.y = im;

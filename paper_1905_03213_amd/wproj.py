@@ -95,6 +95,12 @@ class Kernels:
             self.handle, ms.ctypes.data_as(ctypes.c_void_p), cnt.ctypes.data_as(ctypes.c_void_p)))
         return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(_lib.PHASES)}
 
+    def tuning(self) -> tuple:
+        """wproj_tuning: (tile, chunk) of the tiled gridder."""
+        t, c = ctypes.c_int32(0), ctypes.c_int32(0)
+        _lib.check("wproj_tuning", _lib.lib().wproj_tuning(self.handle, ctypes.byref(t), ctypes.byref(c)))
+        return int(t.value), int(c.value)
+
     def new_grid(self, device="cuda") -> torch.Tensor:
         n, ni = self.params["n"], self.params.get("n_images", 1)
         return torch.zeros((ni, n, n), dtype=self.cplx, device=device)
@@ -150,6 +156,24 @@ def grid(k: Kernels, uvw: torch.Tensor, vis: torch.Tensor, weight: torch.Tensor,
         _ptr(weight_sum, "weight_sum", torch.float64, ni),
         _ptr(counters, "counters", torch.int64, 3),
         _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
+
+
+def autotune(k: Kernels, uvw: torch.Tensor, vis: torch.Tensor, weight: torch.Tensor,
+             image_offsets: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+             stream=None) -> tuple:
+    """wproj_autotune on these visibilities; returns the chosen (tile, chunk)."""
+    nvis = int(uvw.shape[0])
+    n, ni = k.params["n"], k.params.get("n_images", 1)
+    if workspace is None:
+        workspace = k.workspace(nvis)
+    scratch = k.new_grid(device=uvw.device)
+    _lib.check("wproj_autotune", _lib.lib().wproj_autotune(
+        k.handle, nvis, _ptr(uvw, "uvw", torch.float64, 3 * nvis), _ptr(vis, "vis", k.cplx, nvis),
+        _ptr(weight, "weight", k.real, nvis),
+        _ptr(image_offsets, "image_offsets", torch.int64, ni + 1),
+        _ptr(scratch, "scratch_grid", k.cplx, ni * n * n),
+        _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
+    return k.tuning()
 
 
 def degrid(k: Kernels, uvw: torch.Tensor, model_grid: torch.Tensor, vis_out: torch.Tensor,

@@ -74,3 +74,25 @@ def test_hot_tile_split_into_chunks(prec):
     uvw = np.stack([r * np.cos(th) + 30.0 / fov, r * np.sin(th) + 30.0 / fov,
                     rng.uniform(-500, 500, 30000)], axis=1)
     _check({**wl.params, "precision": prec, "algorithm": "tiled"}, uvw, wl.vis, wl.weight)
+
+
+def test_autotune_picks_a_candidate_and_keeps_parity():
+    import paper_1905_03213_amd as W
+    import torch
+
+    wl = synth.small_tracks(n=256, cell=8e-5, n_chan=8, hours=2.0, dt_s=30.0)
+    params = {**wl.params, "precision": "f32", "algorithm": "tiled"}
+    k = W.make_kernels(params)
+    uvw = wl.uvw.cuda()
+    vis = wl.vis.to(torch.complex64).cuda()
+    wt = wl.weight.float().cuda()
+    tile, chunk = W.autotune(k, uvw, vis, wt)
+    assert tile in (16, 32) and chunk in (512, 1024, 2048, 4096, 8192)
+    # a second handle of the same shape reuses the cached choice
+    k2 = W.make_kernels(params)
+    assert W.autotune(k2, uvw, vis, wt) == (tile, chunk)
+    G, sw, cnt, host = run_grid(params, wl.uvw.numpy(), wl.vis.numpy(), wl.weight.numpy(), k=k)
+    (Gr, swr, cr), _, _ = oracle_grid(params, host)
+    assert rel_max(G, Gr) <= TOL["f32"]
+    k.free()
+    k2.free()
