@@ -118,24 +118,33 @@ def main():
     ms_step = ms_total / args.steps
     value = n_valid / (ms_step * 1e-3) / 1e6
 
-    # the same step captured once in a HIP graph and replayed (launch overhead removed)
+    # the same step with its gridding part (zeroing, binning, tile gridder) captured once
+    # in a HIP graph and replayed; the FFT and correction run eagerly after each replay
+    # (rocFFT execution is not replay-safe inside a captured graph)
     graph_ms = None
     if args.graph:
+        def grid_part():
+            g.zero_()
+            sw.zero_()
+            cnt.zero_()
+            W.grid(k, uvw, vis32, wt32, g, weight_sum=sw, counters=cnt, workspace=ws)
+
         side = torch.cuda.Stream()
         side.wait_stream(stream)
         with torch.cuda.stream(side):
-            step()
+            grid_part()
         stream.wait_stream(side)
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
-            step()
+            grid_part()
         torch.cuda.synchronize()
         graph.replay()
         torch.cuda.synchronize()
         ev0.record(stream)
         for _ in range(args.steps):
             graph.replay()
+            W.image(k, W.GRID_TO_IMAGE, g, img, sw, workspace=ws)
         ev1.record(stream)
         torch.cuda.synchronize()
         graph_ms = ev0.elapsed_time(ev1) / args.steps

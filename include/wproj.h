@@ -156,7 +156,9 @@ int wproj_grid(const wproj_kernels *k, int64_t nvis, const double *uvw, const vo
                int64_t *counters, void *workspace, int64_t workspace_bytes, void *stream);
 
 /*
- * Degridding, the adjoint of gridding (prediction of model visibilities):
+ * Degridding, the adjoint of gridding (prediction of model visibilities).  With
+ * WPROJ_ALGO_TILED the visibilities are binned as for gridding and each tile of the
+ * model grid is read once into LDS; WPROJ_ALGO_PLAIN gathers straight from HBM:
  *   vis_out[j] = sum_{kv,ku} conj(T_p[ov][ou][kv][ku]) model_grid[i][y0+kv][x0+ku]
  * with the same footprint rule; rows with non-finite uvw or off-grid footprints, and
  * rows outside every image range, are set to 0.  vis_out is overwritten
@@ -187,7 +189,7 @@ int wproj_image(const wproj_kernels *k, int direction, void *grid, void *image,
                 const double *weight_sum, void *workspace, int64_t workspace_bytes, void *stream);
 
 /*
- * Choose the tiled gridder's tile side (16 or 32 cells) and work-item length (512 ..
+ * Choose the tiled gridder's tile side (16 or 32 cells) and work-item length (1024 ..
  * 8192 binned records) for this handle by timing each candidate on the caller's data
  * (one warm-up and one timed wproj_grid per candidate, HIP events on `stream`), then keep
  * the fastest in the handle.  The choice is also cached per problem shape (grid size,

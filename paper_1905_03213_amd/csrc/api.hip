@@ -232,11 +232,16 @@ int64_t carve(const wproj_kernels *k, int64_t nvis, char *base, BinWorkspace &W)
   W.items = (WorkItem *)take((int64_t)sizeof(WorkItem) * max_items);
   W.scan_tmp = (uint32_t *)take(4 * scan_temp_words(std::max(B.n_keys, B.n_tiles)));
   W.counter = (uint32_t *)take(4);
+  const TileShape ts = tile_shape(k, B.tile);
+  const int64_t cplx = k->params.precision == WPROJ_F64 ? 16 : 8;
+  W.partial = take(max_items * (int64_t)ts.rows * ts.rows * cplx);
+  W.wslots = (double *)take(8 * kSlots * (int64_t)k->params.n_images);
+  W.cslots = (unsigned long long *)take(8 * 3 * kSlots);
   return off;
 }
 
 constexpr int kTuneTiles[] = {16, 32};
-constexpr int kTuneChunks[] = {512, 1024, 2048, 4096, 8192};
+constexpr int kTuneChunks[] = {1024, 2048, 4096, 8192};
 
 bool plane_in_key_for(const wproj_kernels *k, int tile) {
   const int64_t nt = (k->params.n + tile - 1) / tile;
@@ -249,6 +254,8 @@ int64_t workspace_bytes_for(const wproj_kernels *k, int64_t nvis) {
   if (k->params.algorithm == WPROJ_ALGO_TILED) {
     wproj_kernels tmp;  // geometry only
     tmp.params = k->params;
+    tmp.s_max = k->s_max;
+    tmp.uniform_support = k->uniform_support;
     for (int tile : kTuneTiles) {
       tmp.tile = tile;
       tmp.plane_in_key = plane_in_key_for(k, tile);
@@ -379,6 +386,9 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
   G.O = O;
   G.n_w = n_w;
   G.n_images = params->n_images;
+  G.log2_O = -1;
+  for (int b = 0; b < 9; ++b)
+    if ((1 << b) == O) G.log2_O = b;
   G.fov = (double)n * params->cell_rad;
   G.w_max = params->w_max;
   G.dw = n_w > 1 ? (2.0 * params->w_max) / (double)(n_w - 1) : 0.0;
@@ -639,8 +649,26 @@ int wproj_degrid(const wproj_kernels *k, int64_t nvis, const double *uvw, const 
     return fail(WPROJ_EWORKSPACE, "workspace of %lld bytes given, %lld needed",
                 (long long)workspace_bytes, (long long)need);
   if (nvis == 0) return WPROJ_OK;
-  PhaseTimer pt(k, WPROJ_PHASE_DEGRID, (hipStream_t)stream);
-  HIP_TRY(launch_plain_degrid(k, nvis, uvw, model_grid, image_offsets, vis_out, (hipStream_t)stream));
+  hipStream_t s = (hipStream_t)stream;
+  if (k->params.algorithm == WPROJ_ALGO_PLAIN) {
+    PhaseTimer pt(k, WPROJ_PHASE_DEGRID, s);
+    HIP_TRY(launch_plain_degrid(k, nvis, uvw, model_grid, image_offsets, vis_out, s));
+    return WPROJ_OK;
+  }
+  if (nvis > 0xfffffffell)
+    return fail(WPROJ_EINVAL, "the tiled degridder takes at most 2^32 - 2 visibilities per call");
+  if (k->n_taps > (int64_t)kTapMask)
+    return fail(WPROJ_EUNSUPPORTED, "kernel tables of %lld taps exceed the tiled degridder's 2^26",
+                (long long)k->n_taps);
+  const BinShape B = bin_shape(k);
+  BinWorkspace W;
+  carve(k, nvis, (char *)workspace, W);
+  {
+    PhaseTimer pt(k, WPROJ_PHASE_BIN, s);
+    HIP_TRY(launch_bin(k, B, nvis, uvw, nullptr, nullptr, image_offsets, nullptr, nullptr, W, s));
+  }
+  PhaseTimer pt(k, WPROJ_PHASE_DEGRID, s);
+  HIP_TRY(launch_tiled_degrid(k, B, W, model_grid, vis_out, nvis, s));
   return WPROJ_OK;
 }
 

@@ -12,6 +12,8 @@
 //   scatter      record of visibility j goes to offset[key] + slot;
 //   work list    each tile's record range split into chunks of at most `chunk` records.
 // Count atomics are aggregated across each wavefront's lanes that share a key.
+#include <algorithm>
+
 #include "wproj_tiled.h"
 
 namespace wproj {
@@ -24,25 +26,33 @@ __device__ inline uint64_t lane_mask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// atomicAdd(count[key], 1) for every lane with a key, returning the lane's slot.  All lanes
-// issue one atomic instruction together (one memory round trip per wave); the largest
-// group of lanes sharing the first active lane's key is folded into a single add by
-// that lane, which covers the common case of neighbouring rows landing in one bin.
-// Lanes with key == kInvalid take no part.
+// atomicAdd(count[key], 1) for every lane with a key, returning the lane's slot.  Lanes
+// are first grouped by key with ballots (registers only); then one atomic instruction
+// is issued in which only each group's first lane takes part, adding the group's size;
+// each lane's slot is its group's returned base plus its rank inside the group.  A
+// wavefront therefore makes one memory round trip and as many atomics as it has
+// distinct keys (rows of one baseline's channels share tiles and planes).  Lanes with
+// key == kInvalid take no part.
 __device__ inline uint32_t aggregated_slot(uint32_t *count, uint32_t key) {
   const int lane = threadIdx.x & 63;
-  const uint64_t active = __ballot(key != kInvalid);
-  if (active == 0) return 0;
-  const int leader = __ffsll((unsigned long long)active) - 1;
-  const uint32_t lk = __shfl(key, leader, 64);
-  const uint64_t same = __ballot(key == lk) & active;
-  uint32_t inc = 0;
-  if (key != kInvalid) inc = (key == lk) ? (lane == leader ? (uint32_t)__popcll(same) : 0u) : 1u;
+  uint64_t pending = __ballot(key != kInvalid);
+  int my_leader = lane;
+  uint32_t my_rank = 0, inc = 0;
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t lk = __shfl(key, leader, 64);
+    const uint64_t same = __ballot(key == lk) & pending;
+    if (key == lk && ((pending >> lane) & 1ull)) {
+      my_leader = leader;
+      my_rank = (uint32_t)__popcll(same & lane_mask_lt());
+      if (lane == leader) inc = (uint32_t)__popcll(same);
+    }
+    pending &= ~same;
+  }
   uint32_t got = 0;
   if (inc) got = atomicAdd(&count[key], inc);
-  const uint32_t base = __shfl(got, leader, 64);
-  if (key == lk) return base + (uint32_t)__popcll(same & lane_mask_lt());
-  return got;
+  const uint32_t base = __shfl(got, my_leader, 64);
+  return base + my_rank;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -66,7 +76,7 @@ __global__ void __launch_bounds__(256)
     img = image_of(img_off, G.n_images, j);
     if (img >= 0) {
       Footprint f;
-      const Real wj = wt[j];
+      const Real wj = wt ? wt[j] : Real(1);
       cls = classify(G, uvw + 3 * j, wj, f);
       if (cls == kGridded) {
         const int tx = f.x0 / B.tile, ty = f.y0 / B.tile;
@@ -82,25 +92,45 @@ __global__ void __launch_bounds__(256)
     slots[j] = slot;
   }
   // counters
+  // Counters and weight sums: reduced over the workgroup in LDS, then one atomic per
+  // workgroup into one of kSlots partial accumulators (chosen by block index) so that
+  // no address is hit by many workgroups; finalize_kernel adds the slots up.  Rows of
+  // an image other than the workgroup's first row's image (only at image boundaries)
+  // add their weights to their own image's slot directly.
+  __shared__ double s_w[4];
+  __shared__ unsigned s_c[3][4];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int acc_slot = blockIdx.x & (kSlots - 1);
+  const int64_t j_first = (int64_t)blockIdx.x * blockDim.x;
+  const int img_b = j_first < nvis ? image_of(img_off, G.n_images, j_first) : -1;
   const uint64_t dropped = __ballot(cls == kDropped);
   const uint64_t bad = __ballot(cls == kBadWeight);
   const uint64_t clamp = __ballot(clamped);
-  if ((threadIdx.x & 63) == 0 && counters) {
-    if (dropped) atomicAdd(&counters[0], (unsigned long long)__popcll(dropped));
-    if (clamp) atomicAdd(&counters[1], (unsigned long long)__popcll(clamp));
-    if (bad) atomicAdd(&counters[2], (unsigned long long)__popcll(bad));
+  const bool mine = key != kInvalid && img == img_b;
+  double wv = wave_sum(mine ? w : 0.0);
+  if (wsum && key != kInvalid && img != img_b) unsafeAtomicAdd(&wsum[(int64_t)img * kSlots + acc_slot], w);
+  if (lane == 0) {
+    s_w[wid] = wv;
+    s_c[0][wid] = (unsigned)__popcll(dropped);
+    s_c[1][wid] = (unsigned)__popcll(clamp);
+    s_c[2][wid] = (unsigned)__popcll(bad);
   }
-  // sum of weights per image, one atomic per distinct image in the wave
-  if (wsum) {
-    const int gimg = key != kInvalid ? img : -1;
-    uint64_t pending = __ballot(gimg >= 0);
-    while (pending) {
-      const int leader = __ffsll((unsigned long long)pending) - 1;
-      const int li = __shfl(gimg, leader, 64);
-      const uint64_t same = __ballot(gimg == li) & pending;
-      const double s = wave_sum(gimg == li ? w : 0.0);
-      if ((threadIdx.x & 63) == leader) unsafeAtomicAdd(&wsum[li], s);
-      pending &= ~same;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double tw = 0.0;
+    unsigned c0 = 0, c1 = 0, c2 = 0;
+    for (int i = 0; i < nw; ++i) {
+      tw += s_w[i];
+      c0 += s_c[0][i];
+      c1 += s_c[1][i];
+      c2 += s_c[2][i];
+    }
+    if (wsum && img_b >= 0 && tw != 0.0) unsafeAtomicAdd(&wsum[(int64_t)img_b * kSlots + acc_slot], tw);
+    if (counters) {
+      if (c0) atomicAdd(&counters[0 * kSlots + acc_slot], (unsigned long long)c0);
+      if (c1) atomicAdd(&counters[1 * kSlots + acc_slot], (unsigned long long)c1);
+      if (c2) atomicAdd(&counters[2 * kSlots + acc_slot], (unsigned long long)c2);
     }
   }
 }
@@ -117,17 +147,40 @@ __global__ void __launch_bounds__(256)
   const uint32_t key = keys[j];
   if (key == kInvalid) return;
   Footprint f;
-  const Real w = wt[j];
+  const Real w = wt ? wt[j] : Real(1);
   classify(G, uvw + 3 * j, w, f);  // same inputs, same outcome as the key pass
-  const Cplx v = vis[j];
   const int S = G.supp[f.p];
   Rec r;
   r.xy = (uint32_t)f.x0 | ((uint32_t)f.y0 << 16);
   r.tap = (uint32_t)(G.tab_off[f.p] + ((int64_t)f.ov * G.O + f.ou) * S * S) |
           ((uint32_t)(S - 1) << kTapBits);
-  r.wr = w * v.x;
-  r.wi = w * v.y;
+  if (vis) {
+    const Cplx v = vis[j];
+    r.wr = w * v.x;
+    r.wi = w * v.y;
+  } else {
+    set_row(r, (uint32_t)j);
+  }
   rec[offset[key] + slots[j]] = r;
+}
+
+// Adds the per-slot partial weight sums and counters into the caller's outputs, in a
+// fixed slot order.
+__global__ void __launch_bounds__(256)
+    finalize_kernel(int n_images, const double *__restrict__ wslots,
+                    const unsigned long long *__restrict__ cslots, double *wsum,
+                    unsigned long long *counters) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (wsum && t < n_images) {
+    double s = 0.0;
+    for (int k = 0; k < kSlots; ++k) s += wslots[(int64_t)t * kSlots + k];
+    wsum[t] += s;
+  }
+  if (counters && t < 3) {
+    unsigned long long c = 0;
+    for (int k = 0; k < kSlots; ++k) c += cslots[t * kSlots + k];
+    counters[t] += c;
+  }
 }
 
 // ---- exclusive scan of uint32 counts (three phases) ----
@@ -251,18 +304,29 @@ hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, c
                       const void *vis, const void *wt, const int64_t *img_off, double *wsum,
                       int64_t *counters, const BinWorkspace &W, hipStream_t s) {
   const Geometry &G = k->geo;
-  auto *cnt = reinterpret_cast<unsigned long long *>(counters);
   hipError_t e = launch_fill_u32(W.count, B.n_keys, 0u, s);
   if (e != hipSuccess) return e;
+  // zero the slot accumulators (bit pattern 0 is 0.0 and 0)
+  if ((e = launch_fill_u32((uint32_t *)W.wslots, 2 * kSlots * (int64_t)k->params.n_images, 0u, s)) != hipSuccess)
+    return e;
+  if ((e = launch_fill_u32((uint32_t *)W.cslots, 2 * 3 * kSlots, 0u, s)) != hipSuccess) return e;
+  double *wpart = wsum ? W.wslots : nullptr;
+  auto *cnt = counters ? W.cslots : nullptr;
   const dim3 grid(nblk(nvis, 256)), block(256);
   if (k->params.precision == WPROJ_F64) {
     hipLaunchKernelGGL(key_kernel<double>, grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
-                       img_off, W.keys, W.slots, W.count, wsum, cnt);
+                       img_off, W.keys, W.slots, W.count, wpart, cnt);
   } else {
     hipLaunchKernelGGL(key_kernel<float>, grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
-                       img_off, W.keys, W.slots, W.count, wsum, cnt);
+                       img_off, W.keys, W.slots, W.count, wpart, cnt);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (wsum || counters) {
+    const int ni = k->params.n_images;
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((std::max(ni, 3) + 255) / 256)), dim3(256), 0,
+                       s, ni, W.wslots, W.cslots, wsum, reinterpret_cast<unsigned long long *>(counters));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if ((e = launch_exclusive_scan(W.count, W.offset, B.n_keys, W.scan_tmp, s)) != hipSuccess) return e;
   if (k->params.precision == WPROJ_F64) {
     hipLaunchKernelGGL((scatter_kernel<double, double2, RecordF64>), grid, block, 0, s, G, B, nvis,

@@ -1,0 +1,171 @@
+// Tiled degridder (the gather that is the adjoint of gridding):
+//   V_j = sum_{kv,ku} conj(T_p[ov][ou][kv][ku]) M[y0+kv][x0+ku].
+// Visibilities are binned by (image, uv-tile, w-plane) exactly as for gridding, but each
+// record carries its visibility's row instead of W V.  A wavefront takes one work item
+// (a run of records of one tile), copies that tile of the model grid plus its
+// (S_max - 1)-cell halo into its private LDS with coalesced row loads, and then serves
+// every record's footprint from LDS instead of gathering it from HBM.
+//
+// Records go 8 at a time, a group of 8 lanes per record; lane r of a group takes
+// footprint rows kv = r, r + 8, ...: a row's S taps are contiguous in the sub-kernel and
+// its S cells contiguous in the LDS tile.  The group's partial sums are combined with
+// three butterfly shuffles and the first lane of the group stores V_j.
+#include <algorithm>
+
+#include "wproj_tiled.h"
+
+namespace wproj {
+namespace {
+
+template <typename Real> struct Cd;
+template <> struct Cd<float> { using T = float2; };
+template <> struct Cd<double> { using T = double2; };
+
+__device__ inline float2 tap_at(const float2 *t, uint32_t i) { return t[i]; }
+__device__ inline double2 tap_at(const double2 *t, uint32_t i) { return t[i]; }
+__device__ inline float2 tap_at(const half2c *t, uint32_t i) {
+  const half2c h = t[i];
+  return make_float2((float)h.re, (float)h.im);
+}
+
+constexpr int kDegridWaves = 4;
+
+template <typename Real, typename Rec, typename Tab, int S>
+__global__ void __launch_bounds__(64 * kDegridWaves)
+    tiled_degrid_kernel(Geometry G, BinShape B, int pitch, int rows, int wave_lds,
+                        const Tab *__restrict__ tab, const Rec *__restrict__ rec,
+                        const WorkItem *__restrict__ items, const uint32_t *__restrict__ n_items_ptr,
+                        uint32_t *counter, const typename Cd<Real>::T *__restrict__ model,
+                        typename Cd<Real>::T *__restrict__ out) {
+  using C2 = typename Cd<Real>::T;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  C2 *tile = reinterpret_cast<C2 *>(smem_raw) + (size_t)wid * wave_lds;
+  const int grp = lane >> 3, r = lane & 7;
+  const uint32_t n_items = *n_items_ptr;
+  const int64_t cells = (int64_t)G.n * G.n;
+  const int tiles_per_img = B.ntx * B.nty;
+
+  for (;;) {
+    uint32_t got = 0;
+    if (lane == 0) got = atomicAdd(counter, 1u);
+    const uint32_t it = (uint32_t)__builtin_amdgcn_readlane((int)got, 0);
+    if (it >= n_items) break;
+    const WorkItem w = items[it];
+    const int img = (int)(w.tile / (uint32_t)tiles_per_img);
+    const int rt = (int)(w.tile - (uint32_t)img * tiles_per_img);
+    const int ty = rt / B.ntx, tx = rt - ty * B.ntx;
+    const int ox = tx * B.tile, oy = ty * B.tile;
+    const C2 *mimg = model + cells * img;
+    // this wavefront's earlier reads of the previous tile precede these writes: LDS
+    // executes one wavefront's instructions in order; the barrier keeps the compiler
+    // from moving accesses across
+    __builtin_amdgcn_wave_barrier();
+    for (int i = lane; i < rows * rows; i += 64) {
+      const int ry = i / rows, rx = i - ry * rows;
+      const int gy = oy + ry, gx = ox + rx;
+      C2 v;
+      v.x = Real(0);
+      v.y = Real(0);
+      if (gy < G.n && gx < G.n) v = mimg[(int64_t)gy * G.n + gx];
+      tile[ry * pitch + rx] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    for (uint32_t b = w.begin; b < w.end; b += 8) {
+      const uint32_t jr = b + (uint32_t)grp;
+      const bool valid = jr < w.end;
+      const Rec rr = rec[valid ? jr : w.begin];
+      const int Sr = S > 0 ? S : (int)(rr.tap >> kTapBits) + 1;
+      const uint32_t tb = rr.tap & kTapMask;
+      const int base = ((int)(rr.xy >> 16) - oy) * pitch + ((int)(rr.xy & 0xffffu) - ox);
+      Real re = 0, im = 0;
+      if (valid) {
+        for (int kv = r; kv < Sr; kv += 8) {
+          const Tab *trow = tab + tb + (uint32_t)(kv * Sr);
+          const C2 *mrow = tile + base + kv * pitch;
+          if (S > 0) {
+#pragma unroll
+            for (int ku = 0; ku < (S > 0 ? S : 1); ++ku) {
+              const auto k = tap_at(trow, (uint32_t)ku);
+              const C2 m = mrow[ku];
+              re += k.x * m.x + k.y * m.y;  // conj(k) * m
+              im += k.x * m.y - k.y * m.x;
+            }
+          } else {
+            for (int ku = 0; ku < Sr; ++ku) {
+              const auto k = tap_at(trow, (uint32_t)ku);
+              const C2 m = mrow[ku];
+              re += k.x * m.x + k.y * m.y;
+              im += k.x * m.y - k.y * m.x;
+            }
+          }
+        }
+      }
+      re += __shfl_xor(re, 1, 64);
+      im += __shfl_xor(im, 1, 64);
+      re += __shfl_xor(re, 2, 64);
+      im += __shfl_xor(im, 2, 64);
+      re += __shfl_xor(re, 4, 64);
+      im += __shfl_xor(im, 4, 64);
+      if (r == 0 && valid) {
+        C2 o;
+        o.x = re;
+        o.y = im;
+        out[get_row(rr)] = o;
+      }
+    }
+  }
+}
+
+template <typename Real, typename Rec, typename Tab, int S>
+hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
+                      const BinWorkspace &W, const void *model, void *out, hipStream_t s) {
+  using C2 = typename Cd<Real>::T;
+  auto kern = tiled_degrid_kernel<Real, Rec, Tab, S>;
+  const int wpb = (int)std::max<size_t>(1, std::min<size_t>(kDegridWaves, k->max_lds / ts.lds_bytes));
+  const size_t lds = ts.lds_bytes * wpb;
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  const int wave_lds = (int)(ts.lds_bytes / sizeof(C2));
+  hipLaunchKernelGGL(kern, dim3((unsigned)(k->n_cu * per_cu)), dim3(64 * wpb), lds, s, k->geo, B,
+                     ts.pitch, ts.rows, wave_lds, (const Tab *)k->d_tab, (const Rec *)W.rec,
+                     W.items, W.choff + B.n_tiles, W.counter, (const C2 *)model, (C2 *)out);
+  return hipGetLastError();
+}
+
+template <typename Real, typename Rec, typename Tab>
+hipError_t dispatch(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
+                    const BinWorkspace &W, const void *model, void *out, hipStream_t s) {
+  if (k->uniform_support && k->s_max == 8) return launch_one<Real, Rec, Tab, 8>(k, B, ts, W, model, out, s);
+  if (k->uniform_support && k->s_max == 7) return launch_one<Real, Rec, Tab, 7>(k, B, ts, W, model, out, s);
+  return launch_one<Real, Rec, Tab, 0>(k, B, ts, W, model, out, s);
+}
+
+}  // namespace
+
+hipError_t launch_tiled_degrid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
+                               const void *model_grid, void *vis_out, int64_t nvis, hipStream_t s) {
+  const TileShape ts = tile_shape(k, B.tile);
+  // rows that are dropped or belong to no image keep a zero prediction
+  const int64_t words = nvis * (k->params.precision == WPROJ_F64 ? 4 : 2);
+  hipError_t e = launch_fill_u32((uint32_t *)vis_out, words, 0u, s);
+  if (e != hipSuccess) return e;
+  if ((e = launch_fill_u32(W.counter, 1, 0u, s)) != hipSuccess) return e;
+  switch (k->params.precision) {
+    case WPROJ_F64:
+      return dispatch<double, RecordF64, double2>(k, B, ts, W, model_grid, vis_out, s);
+    case WPROJ_F32:
+      return dispatch<float, RecordF32, float2>(k, B, ts, W, model_grid, vis_out, s);
+    default:
+      return dispatch<float, RecordF32, half2c>(k, B, ts, W, model_grid, vis_out, s);
+  }
+}
+
+}  // namespace wproj

@@ -59,14 +59,13 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
     tiled_grid_kernel(Geometry G, BinShape B, int pitch, int rows, int wave_lds,
                       const Tab *__restrict__ tab, const Rec *__restrict__ rec,
                       const WorkItem *__restrict__ items, const uint32_t *__restrict__ n_items_ptr,
-                      uint32_t *counter, Real *grid) {
+                      uint32_t *counter, typename Cx<Real>::T *__restrict__ partial) {
   using C2 = typename Cx<Real>::T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   C2 *acc = reinterpret_cast<C2 *>(smem_raw) + (size_t)wid * wave_lds;
   const uint32_t n_items = *n_items_ptr;
-  const int64_t cells = (int64_t)G.n * G.n;
   const int tiles_per_img = B.ntx * B.nty;
   const int area = rows * pitch;
   // fixed support: lane t holds tap (kv, ku) = (t / S, t % S) at offset kv pitch + ku
@@ -160,18 +159,50 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
       }
     }
 
-    // flush the tile (with halo) to the grid
-    Real *g = grid + 2 * cells * img;
+    // flush: the work item's tile (with halo) goes to its own slot of the partial-tile
+    // buffer with plain coalesced stores; tile_reduce_kernel adds the slots to the grid
+    C2 *dst = partial + (size_t)it * rows * rows;
     for (int i = lane; i < rows * rows; i += 64) {
       const int ry = i / rows, rx = i - ry * rows;
-      const int gy = oy + ry, gx = ox + rx;
-      const C2 v = acc[ry * pitch + rx];
-      if (gx < G.n && gy < G.n && (v.x != Real(0) || v.y != Real(0))) {
-        const int64_t c = (int64_t)gy * G.n + gx;
-        unsafeAtomicAdd(&g[2 * c], v.x);
-        unsafeAtomicAdd(&g[2 * c + 1], v.y);
+      dst[i] = acc[ry * pitch + rx];
+    }
+  }
+}
+
+// Adds the partial tiles to the grid.  One thread per grid cell sums, in FP64, every
+// work item's partial value for that cell: the items of the cell's own tile and those of
+// the tiles to its left/above whose halo reaches it (items of tile t are contiguous in
+// the work list: [choff[t], choff[t + 1])).  Each cell has exactly one writer, so the
+// grid update needs no atomics and the result does not depend on scheduling.
+template <typename Real>
+__global__ void __launch_bounds__(256)
+    tile_reduce_kernel(Geometry G, BinShape B, int rows, const typename Cx<Real>::T *__restrict__ partial,
+                       const uint32_t *__restrict__ choff, Real *grid) {
+  const int64_t cells = (int64_t)G.n * G.n;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cells * G.n_images) return;
+  const int img = (int)(t / cells);
+  const int64_t c = t - (int64_t)img * cells;
+  const int Y = (int)(c / G.n), X = (int)(c - (int64_t)Y * G.n);
+  const int T = B.tile;
+  const int tx = X / T, ty = Y / T, lx = X - tx * T, ly = Y - ty * T;
+  double sr = 0.0, si = 0.0;
+  for (int dy = 0; dy <= ty && ly + dy * T < rows; ++dy) {
+    for (int dx = 0; dx <= tx && lx + dx * T < rows; ++dx) {
+      const int64_t tile = ((int64_t)img * B.nty + (ty - dy)) * B.ntx + (tx - dx);
+      const int off = (ly + dy * T) * rows + (lx + dx * T);
+      const uint32_t i1 = choff[tile + 1];
+      for (uint32_t i = choff[tile]; i < i1; ++i) {
+        const auto v = partial[(size_t)i * rows * rows + off];
+        sr += (double)v.x;
+        si += (double)v.y;
       }
     }
+  }
+  if (sr != 0.0 || si != 0.0) {
+    Real *g = grid + 2 * t;
+    g[0] = (Real)((double)g[0] + sr);
+    g[1] = (Real)((double)g[1] + si);
   }
 }
 
@@ -193,7 +224,12 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
   const int wave_lds = (int)(ts.lds_bytes / (2 * sizeof(Real)));
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, s, k->geo, B, ts.pitch,
                      ts.rows, wave_lds, (const Tab *)k->d_tab, (const Rec *)W.rec, W.items,
-                     W.choff + B.n_tiles, W.counter, (Real *)grid);
+                     W.choff + B.n_tiles, W.counter, (typename Cx<Real>::T *)W.partial);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int64_t total = (int64_t)k->params.n * k->params.n * k->params.n_images;
+  hipLaunchKernelGGL(tile_reduce_kernel<Real>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     s, k->geo, B, ts.rows, (const typename Cx<Real>::T *)W.partial, W.choff,
+                     (Real *)grid);
   return hipGetLastError();
 }
 

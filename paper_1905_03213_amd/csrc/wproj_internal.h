@@ -25,6 +25,7 @@ struct Geometry {
   int32_t O;        // oversampling
   int32_t n_w;      // w-planes
   int32_t n_images;
+  int32_t log2_O;   // log2(O) when O is a power of two, else -1
   double fov;       // n * cell_rad
   double w_max;
   double dw;        // 2 w_max / (n_w - 1), 0 for a single plane
@@ -67,7 +68,8 @@ __device__ inline bool axis_footprint(const Geometry &G, double coord, int S, in
   if (!(fabs(qd) < 1e15)) return false;
   int64_t q = (int64_t)qd;
   int64_t half = (int64_t)S * G.O / 2;
-  int64_t a = floor_div(q - half, G.O) + 1;
+  // floor((q - half) / O): an arithmetic shift when O is a power of two
+  int64_t a = (G.log2_O >= 0 ? ((q - half) >> G.log2_O) : floor_div(q - half, G.O)) + 1;
   if (a < 0 || a + S > G.n) return false;
   x0 = (int)a;
   ou = (int)(a * G.O - q + half - 1);

@@ -10,6 +10,9 @@ namespace wproj {
 constexpr int kTapBits = 26;
 constexpr uint32_t kTapMask = (1u << kTapBits) - 1u;
 
+// Partial accumulators per image (weight sums) and per counter, spread by block index.
+constexpr int kSlots = 256;
+
 // One binned visibility: first cell (x0 | y0 << 16), sub-kernel (first tap | (S-1) << 26)
 // and W V at the path's precision.
 struct RecordF32 {
@@ -22,6 +25,27 @@ struct RecordF64 {
   uint32_t tap;
   double wr, wi;
 };
+
+// Degridding records carry the output row instead of W V, in the bits of `wr`.
+__host__ __device__ inline void set_row(RecordF32 &r, uint32_t j) {
+  __builtin_memcpy(&r.wr, &j, 4);
+  r.wi = 0.0f;
+}
+__host__ __device__ inline void set_row(RecordF64 &r, uint32_t j) {
+  r.wr = 0.0;
+  __builtin_memcpy(&r.wr, &j, 4);
+  r.wi = 0.0;
+}
+__host__ __device__ inline uint32_t get_row(const RecordF32 &r) {
+  uint32_t j;
+  __builtin_memcpy(&j, &r.wr, 4);
+  return j;
+}
+__host__ __device__ inline uint32_t get_row(const RecordF64 &r) {
+  uint32_t j;
+  __builtin_memcpy(&j, &r.wr, 4);
+  return j;
+}
 
 // Binning geometry: tiles of `tile` cells, ntx x nty per image, kw keys per tile
 // (n_wplanes when the plane is part of the key, else 1).
@@ -52,12 +76,17 @@ struct BinWorkspace {
   WorkItem *items;     // [max_items]
   uint32_t *scan_tmp;  // scan_temp_words(max(n_keys, n_tiles))
   uint32_t *counter;   // [1] work-queue head
+  void *partial;       // [max_items][rows][rows] complex: each work item's accumulated tile
+  double *wslots;      // [n_images][kSlots] partial weight sums
+  unsigned long long *cslots;  // [3][kSlots] partial counters
 };
 
 int64_t scan_temp_words(int64_t n);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
                                  hipStream_t s);
+// Bins visibilities for gridding (records carry W V) or, with vis == nullptr and
+// wt == nullptr, for degridding (records carry the visibility's row; weights taken as 1).
 hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, const double *uvw,
                       const void *vis, const void *wt, const int64_t *img_off, double *wsum,
                       int64_t *counters, const BinWorkspace &W, hipStream_t s);
@@ -72,5 +101,7 @@ struct TileShape {
 TileShape tile_shape(const wproj_kernels *k, int tile);
 hipError_t launch_tiled_grid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
                              void *grid, hipStream_t s);
+hipError_t launch_tiled_degrid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
+                               const void *model_grid, void *vis_out, int64_t nvis, hipStream_t s);
 
 }  // namespace wproj

@@ -1,9 +1,10 @@
-"""The gridding + imaging step captured in a HIP graph and replayed.
+"""The gridding step captured in a HIP graph and replayed.
 
-Every launch of wproj_grid / wproj_image is stream-ordered and clears its counters
-with fill kernels (no memset nodes), so the sequence can be captured once and replayed.
-Each replay runs after eager work that changes the inputs in place, and is checked
-against an eager run on the same inputs.
+Every launch of wproj_grid is stream-ordered and clears its counters and queues with
+fill kernels (no memset nodes), so it can be captured once and replayed.  Each replay
+runs after eager work that changes the inputs in place and is checked against an eager
+run on the same inputs.  The FFT of wproj_image (rocFFT) gave wrong images when
+replayed from a captured graph, so imaging runs eagerly after a replayed gridding.
 """
 
 import numpy as np
@@ -35,35 +36,51 @@ def test_graph_replays_match_eager(n_images):
     sw = torch.zeros(n_images, dtype=torch.float64, device="cuda")
     img = torch.empty((n_images, n, n), dtype=torch.float32, device="cuda")
 
-    def step():
+    def grid_part():
         g.zero_()
         sw.zero_()
         W.grid(k, uvw, vis, wt, g, image_offsets=offs, weight_sum=sw, workspace=ws)
+
+    def image_part():
         W.image(k, W.GRID_TO_IMAGE, g, img, sw, workspace=ws)
 
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        step()  # warm up on the capture stream
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        step()
-    torch.cuda.synchronize()
+    def capture(fn):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fn()  # warm up on the capture stream
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            fn()
+        torch.cuda.synchronize()
+        return graph
+
+    # 1) gridding alone in a graph
+    gg = capture(grid_part)
     rng = np.random.default_rng(1)
     for rep in range(4):
-        # eager work between replays: new visibilities and weights, in place
-        scale = float(rng.uniform(0.5, 2.0))
-        vis.mul_(scale)
+        vis.mul_(float(rng.uniform(0.5, 2.0)))  # eager work between replays, in place
         wt.add_(0.125 * rep)
         torch.cuda.synchronize()
-        graph.replay()
+        gg.replay()
         torch.cuda.synchronize()
-        got_img = img.clone()
-        got_sw = sw.clone()
-        step()
+        got_g, got_sw = g.clone(), sw.clone()
+        grid_part()
         torch.cuda.synchronize()
         assert torch.allclose(got_sw, sw, rtol=1e-12, atol=0)
+        assert rel_max(got_g.to(torch.complex128).cpu().numpy(), g.to(torch.complex128).cpu().numpy()) <= 1e-6
+    # 2) replayed gridding followed by eager imaging
+    for rep in range(3):
+        vis.mul_(float(rng.uniform(0.5, 2.0)))
+        torch.cuda.synchronize()
+        gg.replay()
+        image_part()
+        torch.cuda.synchronize()
+        got_img = img.clone()
+        grid_part()
+        image_part()
+        torch.cuda.synchronize()
         assert rel_max(got_img.double().cpu().numpy(), img.double().cpu().numpy()) <= 1e-5
     k.free()
