@@ -35,6 +35,11 @@ S = 8
 LDS_BYTES_PER_VIS = S * S * 16   # complex FP32 read-modify-write per tap
 FLOPS_PER_VIS = S * S * 8        # complex multiply-add per tap
 HBM_BYTES_PER_VIS_GRID = 16      # one binned record read by the tile gridder
+# HBM bytes per launch of tiled_grid_kernel from hardware counters (FETCH_SIZE x2.000 +
+# WRITE_SIZE x1.000, scale factors from a 512 MiB copy), measured at tile 32 / 4096
+# records per work item on this workload; profiles/tiled_grid_kernel_2048_S8_cfg2.md
+# has the commands and raw values.  Reported only when the run uses that configuration.
+MEASURED_TRAFFIC = {"tile": 32, "chunk": 4096, "bytes": 1324.4e6}
 
 
 def log(*a):
@@ -52,6 +57,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the step replayed from a captured HIP graph")
+    ap.add_argument("--tile", type=int, default=0, help="fix the tile side (skips autotuning)")
+    ap.add_argument("--chunk", type=int, default=0, help="fix the work-item length (with --tile)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 512 MiB device buffer 4 times (a kernel of known traffic "
+                         "for scaling hardware byte counters) and exit")
     return ap.parse_args()
 
 
@@ -70,6 +80,14 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float32, device=dev)  # 512 MiB
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": a.numel() * 4, "launches": 4}), flush=True)
+        return
     t0 = time.time()
     wl = synth.cfg2(device=dev, precision="f32", hours=args.hours)
     nvis = wl.nvis
@@ -78,7 +96,8 @@ def main():
     wt32 = wl.weight.to(torch.float32)
     log(f"workload: {nvis} visibilities generated in {time.time() - t0:.1f} s")
 
-    params = {**wl.params, "precision": "f32", "algorithm": "tiled"}
+    params = {**wl.params, "precision": "f32", "algorithm": "tiled", "tile": args.tile,
+              "chunk": args.chunk if args.tile else 0}
     k = W.make_kernels(params)
     n = params["n"]
     g = k.new_grid()
@@ -88,8 +107,12 @@ def main():
     cnt = torch.zeros(3, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
 
-    tile, chunk = W.autotune(k, uvw, vis32, wt32, workspace=ws)
-    log(f"autotuned: tile {tile}, chunk {chunk}")
+    if args.tile:
+        tile, chunk = k.tuning()
+        log(f"fixed: tile {tile}, chunk {chunk}")
+    else:
+        tile, chunk = W.autotune(k, uvw, vis32, wt32, workspace=ws)
+        log(f"autotuned: tile {tile}, chunk {chunk}")
 
     def step():
         g.zero_()
@@ -161,7 +184,8 @@ def main():
         "peak": PEAK_LDS / 1e9,
         "unit": "GB/s",
         "frac": achieved_lds / PEAK_LDS,
-        "traffic": None,
+        "traffic": (MEASURED_TRAFFIC["bytes"] if (tile, chunk) == (MEASURED_TRAFFIC["tile"],
+                                                             MEASURED_TRAFFIC["chunk"]) else None),
         "per_unit": {"unit": "on-grid visibility", "lds_bytes": LDS_BYTES_PER_VIS,
                      "flops": FLOPS_PER_VIS, "hbm_bytes": HBM_BYTES_PER_VIS_GRID},
         "units_per_launch": n_valid,
@@ -260,11 +284,12 @@ def cpu_baseline(wl, seconds):
     tabs = R.kernel_tables(plan)
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     threads = max(1, min(threads, int(os.environ.get("OMP_NUM_THREADS", threads))))
-    # calibrate on a small prefix, then size the timed sample
-    n0 = 200_000
+    # calibrate on a prefix (after one untimed warm-up call), then size the timed sample
+    n0 = 2_000_000
     u = wl.uvw[:n0].cpu().numpy()
     v = wl.vis[:n0].cpu().numpy()
     w = wl.weight[:n0].cpu().numpy()
+    cref.grid(plan, tabs, u[:10000], v[:10000], w[:10000], nthreads=threads)
     t = time.time()
     cref.grid(plan, tabs, u, v, w, nthreads=threads)
     rate = n0 / max(time.time() - t, 1e-3)
@@ -276,8 +301,9 @@ def cpu_baseline(wl, seconds):
     _, sw, _ = cref.grid(plan, tabs, u, v, w, nthreads=threads)
     dt = time.time() - t
     return {"value": float(sw[0]) / dt / 1e6, "unit": "Mvis/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {ns} of {wl.nvis} visibilities (MS order), FP64 C oracle gridder, "
-                      f"OpenMP per-thread grids, {dt:.1f} s"}
+            "sample": (f"{'all' if ns == wl.nvis else 'first ' + str(ns) + ' of'} {wl.nvis} "
+                       f"visibilities (MS order), FP64 C oracle gridder, OpenMP per-thread grids, "
+                       f"{dt:.1f} s")}
 
 
 if __name__ == "__main__":

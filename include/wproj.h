@@ -83,7 +83,9 @@ typedef struct {
   int32_t n_images;         /* >= 1: independent images gridded in one call (e.g. channels) */
   int32_t algorithm;        /* wproj_algorithm */
   int32_t tile;             /* tiled gridder tile side: 0 = default (16), else 16, 32 or 64 */
-  int32_t reserved[5];      /* must be zero */
+  int32_t chunk;            /* tiled gridder work-item length in records: 0 = default (2048),
+                               else 256..65536 */
+  int32_t reserved[4];      /* must be zero */
 } wproj_params;
 
 typedef struct wproj_kernels wproj_kernels; /* opaque handle */

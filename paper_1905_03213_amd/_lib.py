@@ -38,7 +38,8 @@ class Params(ctypes.Structure):
         ("n_images", ctypes.c_int32),
         ("algorithm", ctypes.c_int32),
         ("tile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("chunk", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 

@@ -137,6 +137,8 @@ int validate(const wproj_params *p, std::vector<int32_t> &supp) {
     return fail(WPROJ_EINVAL, "unknown algorithm %d", p->algorithm);
   if (p->tile != 0 && p->tile != 16 && p->tile != 32 && p->tile != 64)
     return fail(WPROJ_EINVAL, "tile must be 0, 16, 32 or 64");
+  if (p->chunk != 0 && (p->chunk < 256 || p->chunk > 65536))
+    return fail(WPROJ_EINVAL, "chunk must be 0 or in [256, 65536]");
   for (int r : p->reserved)
     if (r != 0) return fail(WPROJ_EINVAL, "reserved fields must be zero");
   supp.assign(p->n_wplanes, p->support);
@@ -380,6 +382,7 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
     k->tile = 16;
   }
   k->plane_in_key = plane_in_key_for(k, k->tile);
+  if (params->chunk) k->chunk = params->chunk;
 
   Geometry &G = k->geo;
   G.n = n;

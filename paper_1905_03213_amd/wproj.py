@@ -109,7 +109,7 @@ class Kernels:
 def make_kernels(params: dict, stream=None) -> Kernels:
     """wproj_make_kernels.  params keys: n, cell_rad, n_wplanes, w_max, support,
     support_per_plane (list or None), oversample, kernel_image_size, precision
-    ("f64" | "f32" | "f32_f16table"), n_images, algorithm ("tiled" | "plain"), tile."""
+    ("f64" | "f32" | "f32_f16table"), n_images, algorithm ("tiled" | "plain"), tile, chunk."""
     P = _lib.Params()
     P.n = int(params["n"])
     P.n_wplanes = int(params["n_wplanes"])
@@ -129,6 +129,7 @@ def make_kernels(params: dict, stream=None) -> Kernels:
     algo = params.get("algorithm", "tiled")
     P.algorithm = _ALGO[algo] if isinstance(algo, str) else int(algo)
     P.tile = int(params.get("tile", 0))
+    P.chunk = int(params.get("chunk", 0))
     h = ctypes.c_void_p()
     _lib.check("wproj_make_kernels",
                _lib.lib().wproj_make_kernels(ctypes.byref(P), _stream(stream), ctypes.byref(h)))
