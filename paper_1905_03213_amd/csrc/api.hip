@@ -204,6 +204,9 @@ inline int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; 
 BinShape bin_shape(const wproj_kernels *k) {
   BinShape B;
   B.tile = k->tile;
+  B.log2_tile = 0;
+  while ((1 << B.log2_tile) < k->tile) ++B.log2_tile;
+  B.pitch = tile_shape(k, k->tile).pitch;
   B.ntx = (k->params.n + k->tile - 1) / k->tile;
   B.nty = B.ntx;
   B.kw = k->plane_in_key ? k->params.n_wplanes : 1;

@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256)
       const Real wj = wt ? wt[j] : Real(1);
       cls = classify(G, uvw + 3 * j, wj, f);
       if (cls == kGridded) {
-        const int tx = f.x0 / B.tile, ty = f.y0 / B.tile;
+        const int tx = f.x0 >> B.log2_tile, ty = f.y0 >> B.log2_tile;
         key = (uint32_t)((((int64_t)img * B.nty + ty) * B.ntx + tx) * B.kw + (B.kw > 1 ? f.p : 0));
         w = (double)wj;
         clamped = G.n_w > 1 && fabs(uvw[3 * j + 2]) > G.w_max;
@@ -151,7 +151,8 @@ __global__ void __launch_bounds__(256)
   classify(G, uvw + 3 * j, w, f);  // same inputs, same outcome as the key pass
   const int S = G.supp[f.p];
   Rec r;
-  r.xy = (uint32_t)f.x0 | ((uint32_t)f.y0 << 16);
+  const int lx = f.x0 & (B.tile - 1), ly = f.y0 & (B.tile - 1);
+  r.lds = (uint32_t)(ly * B.pitch + lx);
   r.tap = (uint32_t)(G.tab_off[f.p] + ((int64_t)f.ov * G.O + f.ou) * S * S) |
           ((uint32_t)(S - 1) << kTapBits);
   if (vis) {

@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
       const Rec rr = rec[valid ? jr : w.begin];
       const int Sr = S > 0 ? S : (int)(rr.tap >> kTapBits) + 1;
       const uint32_t tb = rr.tap & kTapMask;
-      const int base = ((int)(rr.xy >> 16) - oy) * pitch + ((int)(rr.xy & 0xffffu) - ox);
+      const int base = (int)rr.lds;
       Real re = 0, im = 0;
       if (valid) {
         for (int kv = r; kv < Sr; kv += 8) {

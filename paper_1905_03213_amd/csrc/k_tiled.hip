@@ -66,7 +66,6 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   C2 *acc = reinterpret_cast<C2 *>(smem_raw) + (size_t)wid * wave_lds;
   const uint32_t n_items = *n_items_ptr;
-  const int tiles_per_img = B.ntx * B.nty;
   const int area = rows * pitch;
   // fixed support: lane t holds tap (kv, ku) = (t / S, t % S) at offset kv pitch + ku
   const int lane_off = S > 0 ? (lane / (S > 0 ? S : 1)) * pitch + lane % (S > 0 ? S : 1) : 0;
@@ -78,24 +77,22 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
     const uint32_t it = (uint32_t)__builtin_amdgcn_readlane((int)got, 0);
     if (it >= n_items) break;
     const WorkItem w = items[it];
-    const int img = (int)(w.tile / (uint32_t)tiles_per_img);
-    const int rt = (int)(w.tile - (uint32_t)img * tiles_per_img);
-    const int ty = rt / B.ntx, tx = rt - ty * B.ntx;
-    const int ox = tx * B.tile, oy = ty * B.tile;
     for (int i = lane; i < area; i += 64) acc[i] = C2{Real(0), Real(0)};
 
     if (S > 0 && S * S <= 64) {
       // Fast path (fixed support, one tap per lane).  Records arrive 64 at a time with
-      // one coalesced load (lane i holds record b + i) and are broadcast with readlane;
-      // the next batch is loaded while this one is processed.  Table taps are loaded one
-      // group of kGroup records ahead of their use.
+      // one coalesced load (lane i holds record i of the batch; the next batch is loaded
+      // while this one is processed) and are broadcast with readlane.  Table taps are
+      // loaded one group of kGroup records ahead of their use.  Padding records of a
+      // partial batch carry zero weight.  (Staging the batch in LDS and reading each record
+      // back as an LDS broadcast measured slower than the readlanes.)
       const uint32_t n_rec = w.end - w.begin;
       auto load_batch = [&](uint32_t b, Rec &dst) {
         const uint32_t i = b + (uint32_t)lane;
         if (i < n_rec) {
           dst = rec[w.begin + i];
         } else {
-          dst.xy = (uint32_t)ox | ((uint32_t)oy << 16);
+          dst.lds = 0;
           dst.tap = 0;
           dst.wr = Real(0);
           dst.wi = Real(0);
@@ -110,8 +107,6 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         Rec nxt;
         const bool more = b + 64 < n_rec;
         if (more) load_batch(b + 64, nxt);
-        // straight-line pipeline over the batch's 8 groups (padding records of a partial
-        // batch carry zero weight): group g+1's taps load while group g accumulates
         Tap c[2][kGroup];
 #pragma unroll
         for (int i = 0; i < kGroup; ++i) c[0][i] = tab_load(tab, (bcast(cur.tap, i) & kTapMask) + tap_lane);
@@ -126,14 +121,14 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
 #pragma unroll
           for (int i = 0; i < kGroup; ++i) {
             const int j = gI * kGroup + i;
-            const uint32_t xy = bcast(cur.xy, j);
-            const Real wr = bcast(cur.wr, j), wi = bcast(cur.wi, j);
-            const int base = ((int)(xy >> 16) - oy) * pitch + ((int)(xy & 0xffffu) - ox);
+            const int base = (int)bcast(cur.lds, j);
+            const Real rwr = bcast(cur.wr, j), rwi = bcast(cur.wi, j);
             if (lane_on) {
-              C2 a = acc[base + lane_off];
-              a.x += wr * c[gI & 1][i].x - wi * c[gI & 1][i].y;
-              a.y += wr * c[gI & 1][i].y + wi * c[gI & 1][i].x;
-              acc[base + lane_off] = a;
+              const int a = base + lane_off;
+              C2 v = acc[a];
+              v.x += rwr * c[gI & 1][i].x - rwi * c[gI & 1][i].y;
+              v.y += rwr * c[gI & 1][i].y + rwi * c[gI & 1][i].x;
+              acc[a] = v;
             }
           }
         }
@@ -147,7 +142,7 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         const uint32_t tp = rr.tap;
         const int Sr = S > 0 ? S : (int)(tp >> kTapBits) + 1;
         const uint32_t tb = tp & kTapMask;
-        const int base = ((int)(rr.xy >> 16) - oy) * pitch + ((int)(rr.xy & 0xffffu) - ox);
+        const int base = (int)rr.lds;
         for (int t = lane; t < Sr * Sr; t += 64) {
           const int kv = t / Sr, ku = t - kv * Sr;
           const auto c = tab_load(tab, tb + t);

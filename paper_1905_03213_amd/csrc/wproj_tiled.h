@@ -13,15 +13,16 @@ constexpr uint32_t kTapMask = (1u << kTapBits) - 1u;
 // Partial accumulators per image (weight sums) and per counter, spread by block index.
 constexpr int kSlots = 256;
 
-// One binned visibility: first cell (x0 | y0 << 16), sub-kernel (first tap | (S-1) << 26)
+// One binned visibility: the LDS offset of its first cell inside its tile's private
+// copy ((y0 - tile y0) pitch + (x0 - tile x0)), its sub-kernel (first tap | (S-1) << 26)
 // and W V at the path's precision.
 struct RecordF32 {
-  uint32_t xy;
+  uint32_t lds;
   uint32_t tap;
   float wr, wi;
 };
 struct RecordF64 {
-  uint32_t xy;
+  uint32_t lds;
   uint32_t tap;
   double wr, wi;
 };
@@ -51,6 +52,8 @@ __host__ __device__ inline uint32_t get_row(const RecordF64 &r) {
 // (n_wplanes when the plane is part of the key, else 1).
 struct BinShape {
   int tile;
+  int log2_tile;     // tile = 1 << log2_tile
+  int pitch;         // LDS row pitch (complex cells) of a tile's private copy
   int ntx, nty;
   int kw;
   int chunk;         // max records per work item
