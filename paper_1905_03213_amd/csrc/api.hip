@@ -227,7 +227,6 @@ int64_t carve(const wproj_kernels *k, int64_t nvis, char *base, BinWorkspace &W)
     off += align_up(bytes);
     return p;
   };
-  W.keys = (uint32_t *)take(4 * nvis);
   W.slots = (uint32_t *)take(4 * nvis);
   W.rec = take(rec_bytes * nvis);
   W.count = (uint32_t *)take(4 * B.n_keys);
@@ -540,6 +539,9 @@ int wproj_grid(const wproj_kernels *k, int64_t nvis, const double *uvw, const vo
     return fail(WPROJ_EUNSUPPORTED, "kernel tables of %lld taps exceed the tiled gridder's 2^26",
                 (long long)k->n_taps);
   const BinShape B = bin_shape(k);
+  if (B.n_keys >= (int64_t)0xffffffffll)
+    return fail(WPROJ_EUNSUPPORTED, "%lld bins (images x tiles) exceed the tiled gridder's 32-bit keys",
+                (long long)B.n_keys);
   BinWorkspace W;
   carve(k, nvis, (char *)workspace, W);
   {
@@ -667,6 +669,9 @@ int wproj_degrid(const wproj_kernels *k, int64_t nvis, const double *uvw, const 
     return fail(WPROJ_EUNSUPPORTED, "kernel tables of %lld taps exceed the tiled degridder's 2^26",
                 (long long)k->n_taps);
   const BinShape B = bin_shape(k);
+  if (B.n_keys >= (int64_t)0xffffffffll)
+    return fail(WPROJ_EUNSUPPORTED, "%lld bins (images x tiles) exceed the tiled degridder's 32-bit keys",
+                (long long)B.n_keys);
   BinWorkspace W;
   carve(k, nvis, (char *)workspace, W);
   {

@@ -11,7 +11,8 @@
 //   scan         exclusive prefix sum of count (Eq. 6);
 //   scatter      record of visibility j goes to offset[key] + slot;
 //   work list    each tile's record range split into chunks of at most `chunk` records.
-// Count atomics are aggregated across each wavefront's lanes that share a key.
+// Count atomics are aggregated over runs of a wavefront's lanes that share a key; the
+// scatter recomputes each visibility's key from its coordinates rather than storing it.
 #include <algorithm>
 
 #include "wproj_tiled.h"
@@ -27,32 +28,34 @@ __device__ inline uint64_t lane_mask_lt() {
 }
 
 // atomicAdd(count[key], 1) for every lane with a key, returning the lane's slot.  Lanes
-// are first grouped by key with ballots (registers only); then one atomic instruction
-// is issued in which only each group's first lane takes part, adding the group's size;
-// each lane's slot is its group's returned base plus its rank inside the group.  A
-// wavefront therefore makes one memory round trip and as many atomics as it has
-// distinct keys (rows of one baseline's channels share tiles and planes).  Lanes with
-// key == kInvalid take no part.
-__device__ inline uint32_t aggregated_slot(uint32_t *count, uint32_t key) {
+// are grouped into runs of consecutive lanes with equal keys (rows of one baseline's
+// channels are adjacent and share tiles and planes, so a wavefront holds a few long
+// runs); the first lane of each run adds the run's length with one atomic, and each lane's
+// slot is its run's returned base plus its distance from the run's first lane.  The cost
+// is a fixed handful of instructions whatever the number of runs; equal keys in separate
+// runs take separate atomics, which leaves the counts and the uniqueness of slots intact.
+// Lanes with key == kInvalid take no part.
+__device__ inline uint32_t run_slot(uint32_t *count, uint32_t key) {
   const int lane = threadIdx.x & 63;
-  uint64_t pending = __ballot(key != kInvalid);
-  int my_leader = lane;
-  uint32_t my_rank = 0, inc = 0;
-  while (pending) {
-    const int leader = __ffsll((unsigned long long)pending) - 1;
-    const uint32_t lk = __shfl(key, leader, 64);
-    const uint64_t same = __ballot(key == lk) & pending;
-    if (key == lk && ((pending >> lane) & 1ull)) {
-      my_leader = leader;
-      my_rank = (uint32_t)__popcll(same & lane_mask_lt());
-      if (lane == leader) inc = (uint32_t)__popcll(same);
-    }
-    pending &= ~same;
-  }
+  const uint32_t prev = __shfl_up(key, 1, 64);
+  const bool start = lane == 0 || key != prev;
+  const uint64_t starts = __ballot(start);
+  const uint64_t upto = (2ull << lane) - 1ull;  // lanes 0..lane (all 64 bits for lane 63)
+  const int leader = 63 - __clzll((long long)(starts & upto));
   uint32_t got = 0;
-  if (inc) got = atomicAdd(&count[key], inc);
-  const uint32_t base = __shfl(got, my_leader, 64);
-  return base + my_rank;
+  if (start && key != kInvalid) {
+    const uint64_t after = starts & ~upto;
+    const int next = after ? __ffsll((unsigned long long)after) - 1 : 64;
+    got = atomicAdd(&count[key], (uint32_t)(next - lane));
+  }
+  return __shfl(got, leader, 64) + (uint32_t)(lane - leader);
+}
+
+// Bin key of a gridded visibility of image img.
+__device__ inline uint32_t bin_key(const BinShape &B, int img, const Footprint &f) {
+  const uint32_t tx = (uint32_t)f.x0 >> B.log2_tile, ty = (uint32_t)f.y0 >> B.log2_tile;
+  const uint32_t tile = ((uint32_t)img * (uint32_t)B.nty + ty) * (uint32_t)B.ntx + tx;
+  return B.kw > 1 ? tile * (uint32_t)B.kw + (uint32_t)f.p : tile;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -64,7 +67,7 @@ template <typename Real>
 __global__ void __launch_bounds__(256)
     key_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
                const Real *__restrict__ wt, const int64_t *__restrict__ img_off,
-               uint32_t *__restrict__ keys, uint32_t *__restrict__ slots, uint32_t *count,
+               uint32_t *__restrict__ slots, uint32_t *count,
                double *wsum, unsigned long long *counters) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t key = kInvalid;
@@ -79,19 +82,14 @@ __global__ void __launch_bounds__(256)
       const Real wj = wt ? wt[j] : Real(1);
       cls = classify(G, uvw + 3 * j, wj, f);
       if (cls == kGridded) {
-        const int tx = f.x0 >> B.log2_tile, ty = f.y0 >> B.log2_tile;
-        key = (uint32_t)((((int64_t)img * B.nty + ty) * B.ntx + tx) * B.kw + (B.kw > 1 ? f.p : 0));
+        key = bin_key(B, img, f);
         w = (double)wj;
         clamped = G.n_w > 1 && fabs(uvw[3 * j + 2]) > G.w_max;
       }
     }
   }
-  const uint32_t slot = aggregated_slot(count, key);
-  if (j < nvis) {
-    keys[j] = key;
-    slots[j] = slot;
-  }
-  // counters
+  const uint32_t slot = run_slot(count, key);
+  if (j < nvis) slots[j] = slot;
   // Counters and weight sums: reduced over the workgroup in LDS, then one atomic per
   // workgroup into one of kSlots partial accumulators (chosen by block index) so that
   // no address is hit by many workgroups; finalize_kernel adds the slots up.  Rows of
@@ -139,21 +137,22 @@ template <typename Real, typename Cplx, typename Rec>
 __global__ void __launch_bounds__(256)
     scatter_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
                    const Cplx *__restrict__ vis, const Real *__restrict__ wt,
-                   const int64_t *__restrict__ img_off, const uint32_t *__restrict__ keys,
-                   const uint32_t *__restrict__ slots, const uint32_t *__restrict__ offset,
-                   Rec *__restrict__ rec) {
+                   const int64_t *__restrict__ img_off, const uint32_t *__restrict__ slots,
+                   const uint32_t *__restrict__ offset, Rec *__restrict__ rec) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nvis) return;
-  const uint32_t key = keys[j];
-  if (key == kInvalid) return;
+  const int img = image_of(img_off, G.n_images, j);
+  if (img < 0) return;
+  // same inputs, same outcome (and key) as the key pass
   Footprint f;
   const Real w = wt ? wt[j] : Real(1);
-  classify(G, uvw + 3 * j, w, f);  // same inputs, same outcome as the key pass
+  if (classify(G, uvw + 3 * j, w, f) != kGridded) return;
+  const uint32_t key = bin_key(B, img, f);
   const int S = G.supp[f.p];
   Rec r;
   const int lx = f.x0 & (B.tile - 1), ly = f.y0 & (B.tile - 1);
   r.lds = (uint32_t)(ly * B.pitch + lx);
-  r.tap = (uint32_t)(G.tab_off[f.p] + ((int64_t)f.ov * G.O + f.ou) * S * S) |
+  r.tap = (uint32_t)(G.tab_off[f.p] + (uint32_t)((f.ov * G.O + f.ou) * S * S)) |
           ((uint32_t)(S - 1) << kTapBits);
   if (vis) {
     const Cplx v = vis[j];
@@ -316,10 +315,10 @@ hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, c
   const dim3 grid(nblk(nvis, 256)), block(256);
   if (k->params.precision == WPROJ_F64) {
     hipLaunchKernelGGL(key_kernel<double>, grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
-                       img_off, W.keys, W.slots, W.count, wpart, cnt);
+                       img_off, W.slots, W.count, wpart, cnt);
   } else {
     hipLaunchKernelGGL(key_kernel<float>, grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
-                       img_off, W.keys, W.slots, W.count, wpart, cnt);
+                       img_off, W.slots, W.count, wpart, cnt);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (wsum || counters) {
@@ -331,11 +330,11 @@ hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, c
   if ((e = launch_exclusive_scan(W.count, W.offset, B.n_keys, W.scan_tmp, s)) != hipSuccess) return e;
   if (k->params.precision == WPROJ_F64) {
     hipLaunchKernelGGL((scatter_kernel<double, double2, RecordF64>), grid, block, 0, s, G, B, nvis,
-                       uvw, (const double2 *)vis, (const double *)wt, img_off, W.keys, W.slots,
+                       uvw, (const double2 *)vis, (const double *)wt, img_off, W.slots,
                        W.offset, (RecordF64 *)W.rec);
   } else {
     hipLaunchKernelGGL((scatter_kernel<float, float2, RecordF32>), grid, block, 0, s, G, B, nvis,
-                       uvw, (const float2 *)vis, (const float *)wt, img_off, W.keys, W.slots,
+                       uvw, (const float2 *)vis, (const float *)wt, img_off, W.slots,
                        W.offset, (RecordF32 *)W.rec);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -39,9 +39,10 @@ struct Footprint {
   int x0, y0, ou, ov, p;
 };
 
-__device__ inline int64_t floor_div(int64_t a, int64_t b) {
-  int64_t q = a / b;
-  if ((a % b) != 0 && ((a < 0) != (b < 0))) q -= 1;
+// floor(a / b) for b > 0
+__device__ inline int floor_div32(int a, int b) {
+  int q = a / b;
+  if (q * b > a) q -= 1;
   return q;
 }
 
@@ -59,20 +60,24 @@ __device__ inline int plane_of(const Geometry &G, double w) {
 // 1/O lattice, first cell x0 = floor((q - S O/2)/O) + 1, sub-kernel ou = x0 O - q + S O/2 - 1.
 // Each product and sum rounds separately, so the integer outcome is a pure function of
 // the float64 inputs.  Returns false when the S cells do not all lie on the grid.
+// An on-grid footprint needs q in [S O/2 - O, (n - S) O + S O/2), inside (-O, (n + 1) O];
+// q outside that interval is rejected in float64 (NaN included), so the integer steps run
+// in 32 bits (n <= 32768 and O <= 256 keep (n + 1) O below 2^24).
 __device__ inline bool axis_footprint(const Geometry &G, double coord, int S, int &x0, int &ou) {
 #pragma clang fp contract(off)
   double g = coord * G.fov;
   g = g + (double)G.n / 2.0;
   double t = g * (double)G.O;
   double qd = floor(t + 0.5);
-  if (!(fabs(qd) < 1e15)) return false;
-  int64_t q = (int64_t)qd;
-  int64_t half = (int64_t)S * G.O / 2;
+  if (!(qd > -(double)G.O && qd <= (double)(G.n + 1) * G.O)) return false;
+  const int q = (int)qd;
+  const int half = S * G.O / 2;
   // floor((q - half) / O): an arithmetic shift when O is a power of two
-  int64_t a = (G.log2_O >= 0 ? ((q - half) >> G.log2_O) : floor_div(q - half, G.O)) + 1;
+  const int d = q - half;
+  const int a = (G.log2_O >= 0 ? (d >> G.log2_O) : floor_div32(d, G.O)) + 1;
   if (a < 0 || a + S > G.n) return false;
-  x0 = (int)a;
-  ou = (int)(a * G.O - q + half - 1);
+  x0 = a;
+  ou = a * G.O - q + half - 1;
   return true;
 }
 

@@ -69,7 +69,6 @@ struct WorkItem {
 
 // Workspace carve-up for one call (all device pointers).
 struct BinWorkspace {
-  uint32_t *keys;      // [nvis]
   uint32_t *slots;     // [nvis]
   void *rec;           // [nvis] RecordF32 / RecordF64
   uint32_t *count;     // [n_keys]
