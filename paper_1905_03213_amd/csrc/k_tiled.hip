@@ -1,9 +1,11 @@
 // Tiled gridder: each work item is a run of binned records of one uv-tile.  One
 // wavefront owns the work item and accumulates its records in a private LDS copy of
-// the tile plus an (S_max - 1)-cell halo on the high-x / high-y sides, then adds the
-// non-zero cells to the grid in HBM with global atomics.  Most of the read-modify-write
-// traffic of gridding therefore stays in LDS instead of going to HBM (the paper's CUDA
-// gridder writes every tap of every visibility to global memory atomically, Section 2.2).
+// the tile plus an (S_max - 1)-cell halo on the high-x / high-y sides, then stores the
+// copy to the work item's slot of a partial-tile buffer; tile_reduce_kernel adds the
+// slots to the grid, one thread per cell in a fixed order (no atomics, deterministic).
+// The read-modify-write traffic of gridding therefore stays in LDS instead of going to
+// HBM (the paper's CUDA gridder updates the grid in global memory with atomics for every
+// tap of every visibility, Section 2.2).
 //
 // Because the tile is private to one wavefront and its 64 lanes always touch 64
 // distinct cells of a record's footprint, the accumulation is a plain LDS read, add and
@@ -15,9 +17,12 @@
 //
 // Launch is persistent: enough wavefronts to fill every CU pull work items from a queue
 // head in HBM until the queue is empty, which evens out the very uneven per-tile
-// visibility counts of Earth-rotation tracks.  Records are read with wave-uniform
-// (scalar) loads in groups of kGroup, and the groups' kernel-table loads are issued
-// together, lane t loading tap t of the record's sub-kernel.
+// visibility counts of Earth-rotation tracks.  With a fixed support of at most 64 taps,
+// lane t handles tap t of every record: records are loaded 64 at a time and broadcast
+// with readlane, and each record's taps come from one buffer load whose wave-uniform
+// part (the sub-kernel) is a scalar offset.  On this chip the step is bound by those
+// table fetches (64 x 8 bytes per record returned to registers, mostly from L1): with
+// FP16 tables (4 bytes per tap) the same launch runs about a third faster.
 #include <algorithm>
 
 #include "wproj_tiled.h"
@@ -31,6 +36,36 @@ __device__ inline float2 tab_load(const half2c *t, uint32_t i) {
   const half2c h = t[i];
   return make_float2((float)h.re, (float)h.im);
 }
+
+// Table fetch through a buffer resource: the sub-kernel's first tap is wave-uniform and
+// goes in the scalar offset, the lane's tap in the vector offset, so the address costs
+// no vector instructions.  The hardware range check covers the vector offset only:
+// callers keep the scalar offset inside the table.
+__device__ inline float2 tab_fetch(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t tap, const float2 *) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, lane * 8u, tap * 8u, 0);
+  // elements are copied out before reinterpretation: a bit cast of a vector element
+  // expression reads the vector's first element
+  const uint32_t re = v[0], im = v[1];
+  return make_float2(__uint_as_float(re), __uint_as_float(im));
+}
+__device__ inline double2 tab_fetch(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t tap, const double2 *) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16u, tap * 16u, 0);
+  const uint32_t w0 = v[0], w1 = v[1], w2 = v[2], w3 = v[3];
+  const uint64_t re = (uint64_t)w0 | ((uint64_t)w1 << 32);
+  const uint64_t im = (uint64_t)w2 | ((uint64_t)w3 << 32);
+  return make_double2(__longlong_as_double((long long)re), __longlong_as_double((long long)im));
+}
+__device__ inline float2 tab_fetch(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t tap, const half2c *) {
+  const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, lane * 4u, tap * 4u, 0);
+  half2c h;
+  __builtin_memcpy(&h, &v, 4);
+  return make_float2((float)h.re, (float)h.im);
+}
+// gfx9 buffer descriptor word 3: 32-bit data format, no swizzle
+constexpr int kBufferWord3 = 0x00020000;
+
+__device__ inline float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 __device__ inline uint32_t bcast(uint32_t v, int j) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, j);
@@ -49,17 +84,31 @@ template <typename Real> struct Cx;
 template <> struct Cx<float> { using T = float2; };
 template <> struct Cx<double> { using T = double2; };
 
-// Records processed per batch by one wavefront: their table loads are all issued
-// before the first is consumed, so up to kGroup memory latencies overlap per wave.
+// Records processed per group by one wavefront in the direct-fetch path: their table
+// loads are all issued before the first is consumed, so up to kGroup memory latencies
+// overlap per wave.
 constexpr int kGroup = 8;
 constexpr int kMaxWavesPerBlock = 4;
 
+// One record's read-add-write of its 64-cell footprint (lane = tap) in the private tile.
+template <typename C2, typename Real, typename Tap>
+__device__ inline void accumulate(C2 *acc, int a, Real wr, Real wi, const Tap &t) {
+  C2 v = acc[a];
+  v.x = fmadd(wr, (Real)t.x, v.x);
+  v.x = fmadd(-wi, (Real)t.y, v.x);
+  v.y = fmadd(wr, (Real)t.y, v.y);
+  v.y = fmadd(wi, (Real)t.x, v.y);
+  acc[a] = v;
+}
+
+// S = fixed support (0 = per-record support).
 template <typename Real, typename Rec, typename Tab, int S>
 __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
     tiled_grid_kernel(Geometry G, BinShape B, int pitch, int rows, int wave_lds,
-                      const Tab *__restrict__ tab, const Rec *__restrict__ rec,
-                      const WorkItem *__restrict__ items, const uint32_t *__restrict__ n_items_ptr,
-                      uint32_t *counter, typename Cx<Real>::T *__restrict__ partial) {
+                      const Tab *__restrict__ tab, uint32_t tab_bytes,
+                      const Rec *__restrict__ rec, const WorkItem *__restrict__ items,
+                      const uint32_t *__restrict__ n_items_ptr, uint32_t *counter,
+                      typename Cx<Real>::T *__restrict__ partial) {
   using C2 = typename Cx<Real>::T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = threadIdx.x & 63;
@@ -70,6 +119,9 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
   // fixed support: lane t holds tap (kv, ku) = (t / S, t % S) at offset kv pitch + ku
   const int lane_off = S > 0 ? (lane / (S > 0 ? S : 1)) * pitch + lane % (S > 0 ? S : 1) : 0;
   const bool lane_on = S > 0 ? lane < S * S : true;
+  const uint32_t tap_lane = lane_on ? (uint32_t)lane : 0u;
+  const __amdgpu_buffer_rsrc_t tab_rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void *)tab, (short)0, (int)tab_bytes, kBufferWord3);
 
   for (;;) {
     uint32_t got = 0;
@@ -78,27 +130,26 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
     if (it >= n_items) break;
     const WorkItem w = items[it];
     for (int i = lane; i < area; i += 64) acc[i] = C2{Real(0), Real(0)};
+    const uint32_t n_rec = w.end - w.begin;
+    // Records arrive 64 at a time with one coalesced load (lane i holds record i of the
+    // batch; the next batch is loaded while this one is processed) and are broadcast to
+    // the wavefront with readlane.
+    auto load_batch = [&](uint32_t b, Rec &dst) {
+      const uint32_t i = b + (uint32_t)lane;
+      if (i < n_rec) {
+        dst = rec[w.begin + i];
+      } else {  // padding records carry zero weight
+        dst.lds = 0;
+        dst.tap = 0;
+        dst.wr = Real(0);
+        dst.wi = Real(0);
+      }
+    };
 
-    if (S > 0 && S * S <= 64) {
-      // Fast path (fixed support, one tap per lane).  Records arrive 64 at a time with
-      // one coalesced load (lane i holds record i of the batch; the next batch is loaded
-      // while this one is processed) and are broadcast with readlane.  Table taps are
-      // loaded one group of kGroup records ahead of their use.  Padding records of a
-      // partial batch carry zero weight.  (Staging the batch in LDS and reading each record
-      // back as an LDS broadcast measured slower than the readlanes.)
-      const uint32_t n_rec = w.end - w.begin;
-      auto load_batch = [&](uint32_t b, Rec &dst) {
-        const uint32_t i = b + (uint32_t)lane;
-        if (i < n_rec) {
-          dst = rec[w.begin + i];
-        } else {
-          dst.lds = 0;
-          dst.tap = 0;
-          dst.wr = Real(0);
-          dst.wi = Real(0);
-        }
-      };
-      const uint32_t tap_lane = lane_on ? (uint32_t)lane : 0u;
+    if constexpr (S > 0 && S * S <= 64) {
+      // Direct-fetch path (fixed support, one tap per lane): table taps are loaded one
+      // group of kGroup records ahead of their use.  (Staging the batch in LDS and
+      // reading each record back as an LDS broadcast measured slower than readlanes.)
       using Tap = decltype(tab_load(tab, 0u));
       constexpr int kGroups = 64 / kGroup;
       Rec cur;
@@ -109,27 +160,21 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         if (more) load_batch(b + 64, nxt);
         Tap c[2][kGroup];
 #pragma unroll
-        for (int i = 0; i < kGroup; ++i) c[0][i] = tab_load(tab, (bcast(cur.tap, i) & kTapMask) + tap_lane);
+        for (int i = 0; i < kGroup; ++i) c[0][i] = tab_fetch(tab_rsrc, tap_lane, bcast(cur.tap, i) & kTapMask, tab);
 #pragma unroll
         for (int gI = 0; gI < kGroups; ++gI) {
           if (gI + 1 < kGroups) {
 #pragma unroll
             for (int i = 0; i < kGroup; ++i)
               c[(gI + 1) & 1][i] =
-                  tab_load(tab, (bcast(cur.tap, (gI + 1) * kGroup + i) & kTapMask) + tap_lane);
+                  tab_fetch(tab_rsrc, tap_lane, bcast(cur.tap, (gI + 1) * kGroup + i) & kTapMask, tab);
           }
 #pragma unroll
           for (int i = 0; i < kGroup; ++i) {
             const int j = gI * kGroup + i;
             const int base = (int)bcast(cur.lds, j);
             const Real rwr = bcast(cur.wr, j), rwi = bcast(cur.wi, j);
-            if (lane_on) {
-              const int a = base + lane_off;
-              C2 v = acc[a];
-              v.x += rwr * c[gI & 1][i].x - rwi * c[gI & 1][i].y;
-              v.y += rwr * c[gI & 1][i].y + rwi * c[gI & 1][i].x;
-              acc[a] = v;
-            }
+            if (lane_on) accumulate(acc, base + lane_off, rwr, rwi, c[gI & 1][i]);
           }
         }
         if (more) cur = nxt;
@@ -145,11 +190,7 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         const int base = (int)rr.lds;
         for (int t = lane; t < Sr * Sr; t += 64) {
           const int kv = t / Sr, ku = t - kv * Sr;
-          const auto c = tab_load(tab, tb + t);
-          C2 a = acc[base + kv * pitch + ku];
-          a.x += rr.wr * c.x - rr.wi * c.y;
-          a.y += rr.wr * c.y + rr.wi * c.x;
-          acc[base + kv * pitch + ku] = a;
+          accumulate(acc, base + kv * pitch + ku, rr.wr, rr.wi, tab_load(tab, tb + t));
         }
       }
     }
@@ -218,8 +259,9 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
   const unsigned blocks = (unsigned)(k->n_cu * per_cu);
   const int wave_lds = (int)(ts.lds_bytes / (2 * sizeof(Real)));
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, s, k->geo, B, ts.pitch,
-                     ts.rows, wave_lds, (const Tab *)k->d_tab, (const Rec *)W.rec, W.items,
-                     W.choff + B.n_tiles, W.counter, (typename Cx<Real>::T *)W.partial);
+                     ts.rows, wave_lds, (const Tab *)k->d_tab, (uint32_t)(k->n_taps * sizeof(Tab)),
+                     (const Rec *)W.rec, W.items, W.choff + B.n_tiles, W.counter,
+                     (typename Cx<Real>::T *)W.partial);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t total = (int64_t)k->params.n * k->params.n * k->params.n_images;
   hipLaunchKernelGGL(tile_reduce_kernel<Real>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
@@ -231,10 +273,8 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
 template <typename Real, typename Rec, typename Tab>
 hipError_t dispatch_support(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
                             const BinWorkspace &W, void *grid, hipStream_t s) {
-  if (k->uniform_support && k->s_max == 8)
-    return launch_one<Real, Rec, Tab, 8>(k, B, ts, W, grid, s);
-  if (k->uniform_support && k->s_max == 7)
-    return launch_one<Real, Rec, Tab, 7>(k, B, ts, W, grid, s);
+  if (k->uniform_support && k->s_max == 8) return launch_one<Real, Rec, Tab, 8>(k, B, ts, W, grid, s);
+  if (k->uniform_support && k->s_max == 7) return launch_one<Real, Rec, Tab, 7>(k, B, ts, W, grid, s);
   return launch_one<Real, Rec, Tab, 0>(k, B, ts, W, grid, s);
 }
 
