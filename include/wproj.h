@@ -215,12 +215,13 @@ int wproj_tuning(const wproj_kernels *k, int32_t *tile, int32_t *chunk);
 /* Phases timed by wproj_profile. */
 typedef enum {
   WPROJ_PHASE_BIN = 0,      /* key/count, scan, scatter, work list (tiled gridding) */
-  WPROJ_PHASE_GRID = 1,     /* the LDS-tile gridder kernel */
+  WPROJ_PHASE_GRID = 1,     /* the LDS-tile gridder kernel (work-queue reset + gridder) */
   WPROJ_PHASE_PLAIN = 2,    /* the plain gridder kernel */
   WPROJ_PHASE_FFT = 3,      /* rocFFT execution inside wproj_image */
   WPROJ_PHASE_CORRECT = 4,  /* grid-correction / pre-correction kernel of wproj_image */
   WPROJ_PHASE_DEGRID = 5,   /* the degridder kernel */
-  WPROJ_N_PHASES = 6
+  WPROJ_PHASE_REDUCE = 6,   /* adding the tile gridder's partial tiles into the grid */
+  WPROJ_N_PHASES = 7
 } wproj_phase;
 
 /*

@@ -21,7 +21,7 @@ STATUS = {0: "WPROJ_OK", -1: "WPROJ_EINVAL", -2: "WPROJ_ENOMEM", -3: "WPROJ_EHIP
 EXPORTED = ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_workspace_size",
             "wproj_grid", "wproj_degrid", "wproj_image", "wproj_autotune", "wproj_tuning",
             "wproj_profile", "wproj_profile_read", "wproj_last_error", "wproj_version")
-PHASES = ("bin", "grid", "plain", "fft", "correct", "degrid")
+PHASES = ("bin", "grid", "plain", "fft", "correct", "degrid", "reduce")
 
 
 class Params(ctypes.Structure):

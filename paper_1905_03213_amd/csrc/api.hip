@@ -552,6 +552,10 @@ int wproj_grid(const wproj_kernels *k, int64_t nvis, const double *uvw, const vo
     PhaseTimer pt(k, WPROJ_PHASE_GRID, s);
     HIP_TRY(launch_tiled_grid(k, B, W, grid, s));
   }
+  {
+    PhaseTimer pt(k, WPROJ_PHASE_REDUCE, s);
+    HIP_TRY(launch_tile_reduce(k, B, W, grid, s));
+  }
   return WPROJ_OK;
 }
 

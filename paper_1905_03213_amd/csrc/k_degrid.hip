@@ -8,8 +8,8 @@
 //
 // Records go 8 at a time, a group of 8 lanes per record; lane r of a group takes
 // footprint rows kv = r, r + 8, ...: a row's S taps are contiguous in the sub-kernel and
-// its S cells contiguous in the LDS tile.  The group's partial sums are combined with
-// three butterfly shuffles and the first lane of the group stores V_j.
+// its S cells contiguous in the LDS tile.  The group's partial sums are combined across
+// its 8 lanes and the first lane of the group stores V_j.
 #include <algorithm>
 
 #include "wproj_tiled.h"
@@ -29,6 +29,28 @@ __device__ inline float2 tap_at(const half2c *t, uint32_t i) {
 }
 
 constexpr int kDegridWaves = 4;
+
+// Sum over each aligned group of 8 lanes, valid in the group's first lane: DPP quad
+// permutes pair lanes 1 and 2 apart, then a row shift brings lane +4.
+__device__ inline float dpp_f(float v, int ctrl) {
+  switch (ctrl) {
+    case 0xB1: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+    case 0x4E: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+    default: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x104, 0xF, 0xF, false));
+  }
+}
+__device__ inline float group8_sum(float v) {
+  v += dpp_f(v, 0xB1);  // quad_perm [1,0,3,2]
+  v += dpp_f(v, 0x4E);  // quad_perm [2,3,0,1]
+  v += dpp_f(v, 0x104); // row_shl:4 (lane i reads lane i + 4 of its row of 16)
+  return v;
+}
+__device__ inline double group8_sum(double v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  return v;
+}
 
 template <typename Real, typename Rec, typename Tab, int S>
 __global__ void __launch_bounds__(64 * kDegridWaves)
@@ -73,47 +95,96 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
     }
     __builtin_amdgcn_wave_barrier();
 
-    for (uint32_t b = w.begin; b < w.end; b += 8) {
-      const uint32_t jr = b + (uint32_t)grp;
-      const bool valid = jr < w.end;
-      const Rec rr = rec[valid ? jr : w.begin];
-      const int Sr = S > 0 ? S : (int)(rr.tap >> kTapBits) + 1;
-      const uint32_t tb = rr.tap & kTapMask;
-      const int base = (int)rr.lds;
-      Real re = 0, im = 0;
-      if (valid) {
-        for (int kv = r; kv < Sr; kv += 8) {
-          const Tab *trow = tab + tb + (uint32_t)(kv * Sr);
-          const C2 *mrow = tile + base + kv * pitch;
-          if (S > 0) {
+    if constexpr (S > 0 && S <= 8) {
+      // Fixed support: records arrive 64 at a time in one coalesced load (lane i holds
+      // record i of the batch; the next batch loads while this one is processed).  Group g
+      // of 8 lanes takes record 8 t + g in step t, fetched from its holder lane with a
+      // shuffle, and its lane r the footprint row kv = r.  A step's taps are loaded one
+      // step ahead, and the group's partial sums are combined with DPP moves.
+      const uint32_t n_rec = w.end - w.begin;
+      auto load_batch = [&](uint32_t b, Rec &dst) {
+        const uint32_t i = b + (uint32_t)lane;
+        dst = rec[w.begin + (i < n_rec ? i : n_rec - 1)];  // padding lanes repeat the last record
+      };
+      auto fetch = [&](const Rec &c, int t, C2 *tap_row, uint32_t &tb_out, int &base_out, uint32_t &row_out) {
+        const int j = t * 8 + grp;
+        const uint32_t tp = (uint32_t)__shfl((int)c.tap, j, 64);
+        base_out = __shfl((int)c.lds, j, 64);
+        row_out = (uint32_t)__shfl((int)get_row(c), j, 64);
+        tb_out = tp & kTapMask;
+        const uint32_t kv = r < S ? (uint32_t)r : 0u;
 #pragma unroll
-            for (int ku = 0; ku < (S > 0 ? S : 1); ++ku) {
+        for (int ku = 0; ku < S; ++ku) {
+          const auto k = tap_at(tab + tb_out + kv * (uint32_t)S, (uint32_t)ku);
+          tap_row[ku].x = k.x;
+          tap_row[ku].y = k.y;
+        }
+      };
+      Rec cur;
+      if (n_rec > 0) load_batch(0, cur);
+      for (uint32_t b = 0; b < n_rec; b += 64) {
+        Rec nxt;
+        const bool more = b + 64 < n_rec;
+        if (more) load_batch(b + 64, nxt);
+        C2 taps[2][S];
+        uint32_t tb[2], row[2];
+        int base[2];
+        fetch(cur, 0, taps[0], tb[0], base[0], row[0]);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int q = t & 1;
+          if (t + 1 < 8) fetch(cur, t + 1, taps[q ^ 1], tb[q ^ 1], base[q ^ 1], row[q ^ 1]);
+          Real re = 0, im = 0;
+          if (r < S) {
+            const C2 *mrow = tile + base[q] + r * pitch;
+#pragma unroll
+            for (int ku = 0; ku < S; ++ku) {
+              const C2 m = mrow[ku];
+              re += taps[q][ku].x * m.x + taps[q][ku].y * m.y;  // conj(k) * m
+              im += taps[q][ku].x * m.y - taps[q][ku].y * m.x;
+            }
+          }
+          re = group8_sum(re);
+          im = group8_sum(im);
+          const uint32_t jr = b + (uint32_t)(t * 8 + grp);
+          if (r == 0 && jr < n_rec) {
+            C2 o;
+            o.x = re;
+            o.y = im;
+            out[row[q]] = o;
+          }
+        }
+        if (more) cur = nxt;
+      }
+    } else {
+      for (uint32_t b = w.begin; b < w.end; b += 8) {
+        const uint32_t jr = b + (uint32_t)grp;
+        const bool valid = jr < w.end;
+        const Rec rr = rec[valid ? jr : w.begin];
+        const int Sr = S > 0 ? S : (int)(rr.tap >> kTapBits) + 1;
+        const uint32_t tb = rr.tap & kTapMask;
+        const int base = (int)rr.lds;
+        Real re = 0, im = 0;
+        if (valid) {
+          for (int kv = r; kv < Sr; kv += 8) {
+            const Tab *trow = tab + tb + (uint32_t)(kv * Sr);
+            const C2 *mrow = tile + base + kv * pitch;
+            for (int ku = 0; ku < Sr; ++ku) {
               const auto k = tap_at(trow, (uint32_t)ku);
               const C2 m = mrow[ku];
               re += k.x * m.x + k.y * m.y;  // conj(k) * m
               im += k.x * m.y - k.y * m.x;
             }
-          } else {
-            for (int ku = 0; ku < Sr; ++ku) {
-              const auto k = tap_at(trow, (uint32_t)ku);
-              const C2 m = mrow[ku];
-              re += k.x * m.x + k.y * m.y;
-              im += k.x * m.y - k.y * m.x;
-            }
           }
         }
-      }
-      re += __shfl_xor(re, 1, 64);
-      im += __shfl_xor(im, 1, 64);
-      re += __shfl_xor(re, 2, 64);
-      im += __shfl_xor(im, 2, 64);
-      re += __shfl_xor(re, 4, 64);
-      im += __shfl_xor(im, 4, 64);
-      if (r == 0 && valid) {
-        C2 o;
-        o.x = re;
-        o.y = im;
-        out[get_row(rr)] = o;
+        re = group8_sum(re);
+        im = group8_sum(im);
+        if (r == 0 && valid) {
+          C2 o;
+          o.x = re;
+          o.y = im;
+          out[get_row(rr)] = o;
+        }
       }
     }
   }

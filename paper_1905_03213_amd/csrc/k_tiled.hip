@@ -262,7 +262,12 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
                      ts.rows, wave_lds, (const Tab *)k->d_tab, (uint32_t)(k->n_taps * sizeof(Tab)),
                      (const Rec *)W.rec, W.items, W.choff + B.n_tiles, W.counter,
                      (typename Cx<Real>::T *)W.partial);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_reduce(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
+                         const BinWorkspace &W, void *grid, hipStream_t s) {
   const int64_t total = (int64_t)k->params.n * k->params.n * k->params.n_images;
   hipLaunchKernelGGL(tile_reduce_kernel<Real>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
                      s, k->geo, B, ts.rows, (const typename Cx<Real>::T *)W.partial, W.choff,
@@ -308,6 +313,13 @@ hipError_t launch_tiled_grid(const wproj_kernels *k, const BinShape &B, const Bi
     default:
       return dispatch_support<float, RecordF32, half2c>(k, B, ts, W, grid, s);
   }
+}
+
+hipError_t launch_tile_reduce(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
+                              void *grid, hipStream_t s) {
+  const TileShape ts = tile_shape(k, B.tile);
+  if (k->params.precision == WPROJ_F64) return launch_reduce<double>(k, B, ts, W, grid, s);
+  return launch_reduce<float>(k, B, ts, W, grid, s);
 }
 
 }  // namespace wproj

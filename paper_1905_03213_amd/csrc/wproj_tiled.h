@@ -101,8 +101,11 @@ struct TileShape {
   size_t lds_bytes;
 };
 TileShape tile_shape(const wproj_kernels *k, int tile);
+// The tile gridder into the work items' partial tiles, then their sum into the grid.
 hipError_t launch_tiled_grid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
                              void *grid, hipStream_t s);
+hipError_t launch_tile_reduce(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
+                              void *grid, hipStream_t s);
 hipError_t launch_tiled_degrid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
                                const void *model_grid, void *vis_out, int64_t nvis, hipStream_t s);
 
