@@ -36,6 +36,10 @@ def _gpu_grid(wl, prec, algo):
     rd = torch.float64 if prec == "f64" else torch.float32
     vis = wl.vis.to(cd)
     wt = wl.weight.to(rd)
+    if algo == "tiled":
+        # the tile and chunk bench.py would time on this data
+        tile, chunk = W.autotune(k, wl.uvw, vis, wt, image_offsets=wl.image_offsets)
+        print(f"[fullsize] autotuned tile {tile}, chunk {chunk}", flush=True)
     g = k.new_grid()
     ni = wl.params.get("n_images", 1)
     sw = torch.zeros(ni, dtype=torch.float64, device="cuda")
