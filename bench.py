@@ -141,33 +141,25 @@ def main():
     ms_step = ms_total / args.steps
     value = n_valid / (ms_step * 1e-3) / 1e6
 
-    # the same step with its gridding part (zeroing, binning, tile gridder) captured once
-    # in a HIP graph and replayed; the FFT and correction run eagerly after each replay
-    # (rocFFT execution is not replay-safe inside a captured graph)
+    # the same step (zeroing, binning, tile gridder, FFT, correction) captured once in a
+    # HIP graph and replayed
     graph_ms = None
     if args.graph:
-        def grid_part():
-            g.zero_()
-            sw.zero_()
-            cnt.zero_()
-            W.grid(k, uvw, vis32, wt32, g, weight_sum=sw, counters=cnt, workspace=ws)
-
         side = torch.cuda.Stream()
         side.wait_stream(stream)
         with torch.cuda.stream(side):
-            grid_part()
+            step()
         stream.wait_stream(side)
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
-            grid_part()
+            step()
         torch.cuda.synchronize()
         graph.replay()
         torch.cuda.synchronize()
         ev0.record(stream)
         for _ in range(args.steps):
             graph.replay()
-            W.image(k, W.GRID_TO_IMAGE, g, img, sw, workspace=ws)
         ev1.record(stream)
         torch.cuda.synchronize()
         graph_ms = ev0.elapsed_time(ev1) / args.steps
@@ -207,7 +199,40 @@ def main():
     k.profile(False)
     degrid_ms = dph["degrid"][0] / max(dph["degrid"][1], 1)
 
+    # rows regrouped by baseline (Eqs. 5 and 6) and the rows of uvw and visibilities
+    # gathered into that order: the paper's GPU-side data preparation, on the same rows
+    src = wl.sources
+    n_t, n_bl, n_ch = int(src["n_time"]), int(src["n_bl"]), int(src["n_chan"])
+    n_ant = int(max(np.max(src["ant1"]), np.max(src["ant2"]))) + 1
+    a1 = torch.as_tensor(np.tile(src["ant1"], n_t).astype(np.int32), device=dev)
+    a2 = torch.as_tensor(np.tile(src["ant2"], n_t).astype(np.int32), device=dev)
+    uvw_rows = uvw.view(n_t * n_bl, n_ch, 3)
+    vis_rows = vis32.view(n_t * n_bl, n_ch)
+    uvw_out = torch.empty_like(uvw_rows)
+    vis_out = torch.empty_like(vis_rows)
+    perm, _, _ = W.regroup_rows(a1, a2, n_ant)
+    torch.cuda.synchronize()
+    reps = 5
+    ev0.record(stream)
+    for _ in range(reps):
+        perm, _, _ = W.regroup_rows(a1, a2, n_ant)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    regroup_ms = ev0.elapsed_time(ev1) / reps
+    ev0.record(stream)
+    for _ in range(reps):
+        W.gather_rows(perm, uvw_rows, out=uvw_out)
+        W.gather_rows(perm, vis_rows, out=vis_out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    gather_ms = ev0.elapsed_time(ev1) / reps
+    gather_bytes = 2 * (uvw_rows.numel() * 8 + vis_rows.numel() * 8)
+    del uvw_out, vis_out, perm, a1, a2
+
     extra = {"phases_ms": per, "degrid": {"ms": degrid_ms, "mvis_per_s": n_valid / degrid_ms / 1e3},
+             "regroup_by_baseline": {"rows": n_t * n_bl, "ms": regroup_ms,
+                                     "gather_uvw_vis_ms": gather_ms,
+                                     "gather_gb_per_s": gather_bytes / gather_ms / 1e6},
              "tuning": {"tile": tile, "chunk": chunk},
              "graph_replay_ms_per_step": graph_ms,
              "counters": {"dropped": counters[0], "w_clamped": counters[1], "bad_weight": counters[2]},

@@ -237,6 +237,41 @@ typedef enum {
 int wproj_profile(wproj_kernels *k, int enable);
 int wproj_profile_read(wproj_kernels *k, double *ms, int64_t *count);
 
+/*
+ * Rows regrouped by baseline (Section 2.2, Eqs. 5 and 6): the preprocessing of the
+ * paper's GPU imager, which groups the rows of a measurement set (one timestamp of one
+ * baseline, all channels; stored in time order) by baseline, keeping time order inside
+ * each baseline.  For rows j = 0 .. n_rows - 1 with 0-based antenna IDs ant1[j], ant2[j]:
+ *   I_B(j)    = (-S^2 + 2 S n_ant + S)/2 + |ant1[j] - ant2[j]|, S = min(ant1[j], ant2[j])
+ *               (Eq. 5), which numbers every antenna pair, autocorrelations included,
+ *               0 .. n_b - 1 with n_b = n_ant (n_ant + 1)/2; a row with an ID outside
+ *               [0, n_ant) gets I_B = n_b and goes last;
+ *   counts[b] = number of rows with I_B = b (the array C), b = 0 .. n_b;
+ *   start[b]  = sum of counts[b'] over b' < b (Eq. 6), b = 0 .. n_b;
+ *   perm[k]   = the row placed at position k: rows in increasing I_B, each baseline's
+ *               rows in their original order (a stable counting sort).
+ * ant1, ant2: int32 [n_rows]; perm: int64 [n_rows]; start, counts: int64 [n_b + 1] (all
+ * device).  n_rows in [0, 2^31 - 1]; n_ant in [1, 255] (WPROJ_EUNSUPPORTED above: one
+ * counter per baseline is kept in LDS).  The workspace (device, caller-owned, scratch)
+ * must hold wproj_regroup_workspace_size(n_rows, n_ant) bytes.
+ * Errors: WPROJ_EINVAL, WPROJ_EUNSUPPORTED, WPROJ_EWORKSPACE, WPROJ_EHIP.
+ */
+int64_t wproj_regroup_workspace_size(int64_t n_rows, int32_t n_ant);
+int wproj_regroup_rows(int64_t n_rows, const int32_t *ant1, const int32_t *ant2, int32_t n_ant,
+                       int64_t *perm, int64_t *start, int64_t *counts, void *workspace,
+                       int64_t workspace_bytes, void *stream);
+
+/*
+ * Row gather, e.g. to apply a regroup permutation to the rows of uvw, visibilities or
+ * weights: dst row k = src row perm[k], k = 0 .. n_rows - 1, rows of row_bytes bytes (a
+ * positive multiple of 4; src and dst 4-byte aligned and not overlapping).  perm: int64
+ * [n_rows] (device).  An entry outside [0, n_src_rows) leaves its destination row
+ * unchanged and adds 1 to *bad (device int64, nullable, accumulated into).
+ * Errors: WPROJ_EINVAL, WPROJ_EHIP.
+ */
+int wproj_gather_rows(int64_t n_rows, int64_t row_bytes, const int64_t *perm, int64_t n_src_rows,
+                      const void *src, void *dst, int64_t *bad, void *stream);
+
 /* Message describing the last non-OK status returned on the calling thread ("" if none). */
 const char *wproj_last_error(void);
 

@@ -17,9 +17,11 @@ from .wproj import (  # noqa: F401
     WprojError,
     autotune,
     degrid,
+    gather_rows,
     grid,
     image,
     last_error,
     make_kernels,
+    regroup_rows,
     version,
 )

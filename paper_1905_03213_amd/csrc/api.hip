@@ -733,3 +733,55 @@ int wproj_image(const wproj_kernels *k, int direction, void *grid, void *image,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Rows regrouped by baseline (Section 2.2, Eqs. 5 and 6) and row gathers.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int32_t kMaxRegroupAnt = 255;  // n_ant (n_ant + 1)/2 + 1 counters fit in LDS
+
+int check_regroup_args(int64_t n_rows, int32_t n_ant) {
+  if (n_rows < 0 || n_rows > 0x7fffffffll) return fail(WPROJ_EINVAL, "n_rows must be in [0, 2^31 - 1]");
+  if (n_ant < 1) return fail(WPROJ_EINVAL, "n_ant must be >= 1");
+  if (n_ant > kMaxRegroupAnt)
+    return fail(WPROJ_EUNSUPPORTED, "n_ant = %d: the regroup keeps one counter per baseline in LDS (n_ant <= %d)",
+                n_ant, kMaxRegroupAnt);
+  return WPROJ_OK;
+}
+}  // namespace
+
+int64_t wproj_regroup_workspace_size(int64_t n_rows, int32_t n_ant) {
+  g_err.clear();
+  const int rc = check_regroup_args(n_rows, n_ant);
+  if (rc != WPROJ_OK) return rc;
+  return regroup_workspace_bytes(regroup_shape(n_rows, n_ant));
+}
+
+int wproj_regroup_rows(int64_t n_rows, const int32_t *ant1, const int32_t *ant2, int32_t n_ant,
+                       int64_t *perm, int64_t *start, int64_t *counts, void *workspace,
+                       int64_t workspace_bytes, void *stream) {
+  g_err.clear();
+  const int rc = check_regroup_args(n_rows, n_ant);
+  if (rc != WPROJ_OK) return rc;
+  if (n_rows > 0 && (!ant1 || !ant2 || !perm)) return fail(WPROJ_EINVAL, "ant1, ant2 or perm is NULL");
+  if (!start || !counts) return fail(WPROJ_EINVAL, "start or counts is NULL");
+  const RegroupShape r = regroup_shape(n_rows, n_ant);
+  const int64_t need = regroup_workspace_bytes(r);
+  if (!workspace || workspace_bytes < need)
+    return fail(WPROJ_EWORKSPACE, "workspace of %lld bytes given, %lld needed", (long long)workspace_bytes,
+                (long long)need);
+  HIP_TRY(launch_regroup(r, n_rows, ant1, ant2, n_ant, perm, start, counts, workspace,
+                         (hipStream_t)stream));
+  return WPROJ_OK;
+}
+
+int wproj_gather_rows(int64_t n_rows, int64_t row_bytes, const int64_t *perm, int64_t n_src_rows,
+                      const void *src, void *dst, int64_t *bad, void *stream) {
+  g_err.clear();
+  if (n_rows < 0 || n_src_rows < 0) return fail(WPROJ_EINVAL, "n_rows and n_src_rows must be >= 0");
+  if (row_bytes <= 0 || (row_bytes & 3)) return fail(WPROJ_EINVAL, "row_bytes must be a positive multiple of 4");
+  if (n_rows > 0 && (!perm || !src || !dst)) return fail(WPROJ_EINVAL, "perm, src or dst is NULL");
+  HIP_TRY(launch_gather_rows(n_rows, row_bytes, perm, n_src_rows, src, dst, bad, (hipStream_t)stream));
+  return WPROJ_OK;
+}
+

@@ -109,4 +109,22 @@ hipError_t launch_tile_reduce(const wproj_kernels *k, const BinShape &B, const B
 hipError_t launch_tiled_degrid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
                                const void *model_grid, void *vis_out, int64_t nvis, hipStream_t s);
 
+// Rows regrouped by baseline (Eqs. 5 and 6): a stable counting sort over blocks of
+// rows_per_block rows, n_keys = n_ant (n_ant + 1) / 2 baseline numbers + 1 for rows with
+// an invalid antenna ID.
+struct RegroupShape {
+  uint32_t n_keys;
+  int64_t rows_per_block;
+  int64_t n_blocks;
+  int64_t n_counts;  // n_keys * n_blocks
+};
+RegroupShape regroup_shape(int64_t n_rows, int32_t n_ant);
+int64_t regroup_workspace_bytes(const RegroupShape &r);
+hipError_t launch_regroup(const RegroupShape &r, int64_t n_rows, const int32_t *ant1,
+                          const int32_t *ant2, int32_t n_ant, int64_t *perm, int64_t *start,
+                          int64_t *counts, void *workspace, hipStream_t s);
+hipError_t launch_gather_rows(int64_t n_rows, int64_t row_bytes, const int64_t *perm,
+                              int64_t n_src_rows, const void *src, void *dst, int64_t *bad,
+                              hipStream_t s);
+
 }  // namespace wproj

@@ -208,6 +208,46 @@ def image(k: Kernels, direction: int, grid_buf: torch.Tensor, image_buf: torch.T
         _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
 
 
+def regroup_rows(ant1: torch.Tensor, ant2: torch.Tensor, n_ant: int, stream=None):
+    """wproj_regroup_rows (Eqs. 5 and 6): returns (perm, start, counts), int64 device tensors;
+    rows in increasing baseline number, time order kept inside each baseline."""
+    n_rows = int(ant1.shape[0])
+    if int(ant2.shape[0]) != n_rows:
+        raise ValueError("ant1 and ant2 differ in length")
+    n_keys = n_ant * (n_ant + 1) // 2 + 1
+    need = int(_lib.lib().wproj_regroup_workspace_size(n_rows, int(n_ant)))
+    if need < 0:
+        raise _lib.WprojError("wproj_regroup_workspace_size", need, last_error())
+    dev = ant1.device
+    perm = torch.empty(n_rows, dtype=torch.int64, device=dev)
+    start = torch.empty(n_keys, dtype=torch.int64, device=dev)
+    counts = torch.empty(n_keys, dtype=torch.int64, device=dev)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _lib.check("wproj_regroup_rows", _lib.lib().wproj_regroup_rows(
+        n_rows, _ptr(ant1, "ant1", torch.int32, n_rows), _ptr(ant2, "ant2", torch.int32, n_rows),
+        int(n_ant), _ptr(perm, "perm", torch.int64, n_rows), _ptr(start, "start", torch.int64, n_keys),
+        _ptr(counts, "counts", torch.int64, n_keys), _ptr(ws, "workspace", torch.uint8), ws.numel(),
+        _stream(stream)))
+    return perm, start, counts
+
+
+def gather_rows(perm: torch.Tensor, src: torch.Tensor, out: Optional[torch.Tensor] = None,
+                bad: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """wproj_gather_rows: out[k] = src[perm[k]] over the first dimension of src."""
+    n_rows = int(perm.shape[0])
+    n_src = int(src.shape[0])
+    row_bytes = src[0].numel() * src.element_size() if n_src else src.element_size()
+    if out is None:
+        out = torch.empty((n_rows,) + tuple(src.shape[1:]), dtype=src.dtype, device=src.device)
+    if not src.is_contiguous() or not out.is_contiguous():
+        raise ValueError("src and out must be contiguous")
+    _lib.check("wproj_gather_rows", _lib.lib().wproj_gather_rows(
+        n_rows, row_bytes, _ptr(perm, "perm", torch.int64, n_rows), n_src,
+        _ptr(src, "src") if n_src else None, _ptr(out, "out") if n_rows else None,
+        _ptr(bad, "bad", torch.int64, 1), _stream(stream)))
+    return out
+
+
 def last_error() -> str:
     return _lib.lib().wproj_last_error().decode()
 

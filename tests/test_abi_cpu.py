@@ -71,3 +71,25 @@ def test_null_handle_paths():
     assert L.wproj_image(None, 0, None, None, None, None, 0, None) == -1
     assert L.wproj_export(None, 0, None, 0, None, None) == -1
     assert L.wproj_free_kernels(None) == 0
+
+
+def test_regroup_and_gather_argument_checks():
+    L = _lib.lib()
+    assert L.wproj_regroup_workspace_size(-1, 27) == -1
+    assert L.wproj_regroup_workspace_size(10, 0) == -1
+    assert L.wproj_regroup_workspace_size(10, 256) == -4  # one LDS counter per baseline
+    assert L.wproj_regroup_workspace_size(1 << 31, 27) == -1
+    # workspace: per-block counts (blocks of >= 2048 rows), their scan and the scan's carries
+    ws = L.wproj_regroup_workspace_size(1_010_880, 27)
+    blocks = -(-1_010_880 // 2048)
+    keys = 27 * 28 // 2 + 1
+    assert ws >= 4 * (2 * keys * blocks + 1)
+    assert L.wproj_regroup_workspace_size(0, 1) > 0
+    # NULL outputs and a short workspace are rejected before any GPU work
+    assert L.wproj_regroup_rows(4, None, None, 27, None, None, None, None, 0, None) == -1
+    fake = ctypes.c_void_p(16)
+    assert L.wproj_regroup_rows(4, fake, fake, 27, fake, fake, fake, fake, 8, None) == -5
+    assert L.wproj_gather_rows(4, 6, fake, 4, fake, fake, None, None) == -1   # row_bytes % 4
+    assert L.wproj_gather_rows(4, 0, fake, 4, fake, fake, None, None) == -1
+    assert L.wproj_gather_rows(-1, 8, fake, 4, fake, fake, None, None) == -1
+    assert L.wproj_gather_rows(4, 8, None, 4, fake, fake, None, None) == -1

@@ -1,14 +1,13 @@
 """The gridding step captured in a HIP graph and replayed.
 
-Every launch of wproj_grid is stream-ordered and clears its counters and queues with
-fill kernels (no memset nodes), so it can be captured once and replayed.  Each replay
-runs after eager work that changes the inputs in place and is checked against an eager
-run on the same inputs.  The FFT of wproj_image (rocFFT) gave wrong images when
-replayed from a captured graph, so imaging runs eagerly after a replayed gridding.
-Record order inside a tile follows the binning's atomic slot assignment, so FP32
-grids of two runs agree to rounding (~1e-7), not bit for bit; images are compared on
-the inner half, away from the edge pixels where the grid correction kappa^2 (~1e6)
-amplifies that rounding.
+Every launch of wproj_grid and wproj_image is stream-ordered and clears its counters
+and queues with fill kernels (no memset nodes), so it can be captured once and
+replayed.  Each replay runs after eager work that changes the inputs in place and is
+checked against an eager run on the same inputs: gridding alone, then the whole step
+(gridding, rocFFT inverse, correction) in one graph.  Record order inside a tile follows
+the binning's atomic slot assignment, so FP32 grids of two runs agree to rounding
+(~1e-7), not bit for bit; images are compared on the inner half, away from the edge
+pixels where the grid correction kappa^2 (~1e6) amplifies that rounding.
 """
 
 import numpy as np
@@ -75,16 +74,19 @@ def test_graph_replays_match_eager(n_images):
         torch.cuda.synchronize()
         assert torch.allclose(got_sw, sw, rtol=1e-12, atol=0)
         assert rel_max(got_g.to(torch.complex128).cpu().numpy(), g.to(torch.complex128).cpu().numpy()) <= 1e-6
-    # 2) replayed gridding followed by eager imaging
+    # 2) the whole step (gridding, FFT, correction) in one graph
+    def step():
+        grid_part()
+        image_part()
+
+    gs = capture(step)
     for rep in range(3):
         vis.mul_(float(rng.uniform(0.5, 2.0)))
         torch.cuda.synchronize()
-        gg.replay()
-        image_part()
+        gs.replay()
         torch.cuda.synchronize()
         got_img = img.clone()
-        grid_part()
-        image_part()
+        step()
         torch.cuda.synchronize()
         q = n // 4
         assert rel_max(got_img[:, q:-q, q:-q].double().cpu().numpy(),
