@@ -238,6 +238,22 @@ int wproj_profile(wproj_kernels *k, int enable);
 int wproj_profile_read(wproj_kernels *k, double *ms, int64_t *count);
 
 /*
+ * Per-visibility footprint: the uvw -> grid step every gridding and degridding call
+ * takes, exported.  For visibility j, out[6 j .. 6 j + 5] (int32, device) =
+ * {x0, y0, ou, ov, p, class}: first footprint cell (x0, y0), sub-kernel (ou, ov), w-plane
+ * p, and class 0 = gridded, 1 = flagged (weight 0), 2 = weight negative or non-finite,
+ * 3 = dropped (non-finite uvw or footprint off the grid).  With
+ *   g = u FoV + n/2, q = floor(g O + 1/2), x0 = floor((q - S O/2)/O) + 1,
+ *   ou = x0 O - q + S O/2 - 1  (the same for v, y0, ov),
+ *   p = nearest plane of w, ties up, clamped to [0, n_wplanes - 1]  (S = S_p),
+ * every product and sum rounded separately in float64.  Rows of class != 0 carry -1
+ * for x0 .. p.  weight: float64 for WPROJ_F64, float32 otherwise, nullable (all 1).
+ * Errors: WPROJ_EINVAL, WPROJ_EHIP.
+ */
+int wproj_footprints(const wproj_kernels *k, int64_t nvis, const double *uvw, const void *weight,
+                     int32_t *out, void *stream);
+
+/*
  * Rows regrouped by baseline (Section 2.2, Eqs. 5 and 6): the preprocessing of the
  * paper's GPU imager, which groups the rows of a measurement set (one timestamp of one
  * baseline, all channels; stored in time order) by baseline, keeping time order inside

@@ -17,6 +17,7 @@ from .wproj import (  # noqa: F401
     WprojError,
     autotune,
     degrid,
+    footprints,
     gather_rows,
     grid,
     image,

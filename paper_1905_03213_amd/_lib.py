@@ -21,7 +21,8 @@ STATUS = {0: "WPROJ_OK", -1: "WPROJ_EINVAL", -2: "WPROJ_ENOMEM", -3: "WPROJ_EHIP
 EXPORTED = ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_workspace_size",
             "wproj_grid", "wproj_degrid", "wproj_image", "wproj_autotune", "wproj_tuning",
             "wproj_profile", "wproj_profile_read", "wproj_last_error", "wproj_version",
-            "wproj_regroup_workspace_size", "wproj_regroup_rows", "wproj_gather_rows")
+            "wproj_footprints", "wproj_regroup_workspace_size", "wproj_regroup_rows",
+            "wproj_gather_rows")
 PHASES = ("bin", "grid", "plain", "fft", "correct", "degrid", "reduce")
 
 
@@ -78,13 +79,15 @@ def lib():
     L.wproj_last_error.restype = ctypes.c_char_p
     L.wproj_last_error.argtypes = []
     L.wproj_version.argtypes = []
+    L.wproj_footprints.argtypes = [vp, i64, vp, vp, vp, vp]
     L.wproj_regroup_workspace_size.argtypes = [i64, ctypes.c_int32]
     L.wproj_regroup_workspace_size.restype = i64
     L.wproj_regroup_rows.argtypes = [i64, vp, vp, ctypes.c_int32, vp, vp, vp, vp, i64, vp]
     L.wproj_gather_rows.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp]
     for name in ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_grid",
                  "wproj_degrid", "wproj_image", "wproj_autotune", "wproj_tuning", "wproj_profile",
-                 "wproj_profile_read", "wproj_version", "wproj_regroup_rows", "wproj_gather_rows"):
+                 "wproj_profile_read", "wproj_version", "wproj_footprints", "wproj_regroup_rows",
+                 "wproj_gather_rows"):
         getattr(L, name).restype = i32
     _lib = L
     return L

@@ -734,6 +734,16 @@ int wproj_image(const wproj_kernels *k, int direction, void *grid, void *image,
 
 }  // extern "C"
 
+int wproj_footprints(const wproj_kernels *k, int64_t nvis, const double *uvw, const void *weight,
+                     int32_t *out, void *stream) {
+  g_err.clear();
+  if (!k) return fail(WPROJ_EINVAL, "handle is NULL");
+  if (nvis < 0) return fail(WPROJ_EINVAL, "nvis < 0");
+  if (nvis > 0 && (!uvw || !out)) return fail(WPROJ_EINVAL, "uvw or out is NULL");
+  HIP_TRY(launch_footprints(k, nvis, uvw, weight, out, (hipStream_t)stream));
+  return WPROJ_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Rows regrouped by baseline (Section 2.2, Eqs. 5 and 6) and row gathers.
 // ---------------------------------------------------------------------------

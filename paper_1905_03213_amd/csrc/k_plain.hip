@@ -195,4 +195,41 @@ hipError_t launch_plain_degrid(const wproj_kernels *k, int64_t nvis, const doubl
   return hipGetLastError();
 }
 
+namespace {
+
+// One thread per visibility: its footprint and class, exactly as every gridding and
+// degridding kernel decides them.
+template <typename Real>
+__global__ void __launch_bounds__(256)
+    footprint_kernel(Geometry G, int64_t nvis, const double *__restrict__ uvw,
+                     const Real *__restrict__ wt, int32_t *__restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nvis) return;
+  Footprint f;
+  const int cls = classify(G, uvw + 3 * j, wt ? wt[j] : Real(1), f);
+  int32_t *o = out + 6 * j;
+  const bool on = cls == kGridded;
+  o[0] = on ? f.x0 : -1;
+  o[1] = on ? f.y0 : -1;
+  o[2] = on ? f.ou : -1;
+  o[3] = on ? f.ov : -1;
+  o[4] = on ? f.p : -1;
+  o[5] = cls;
+}
+
+}  // namespace
+
+hipError_t launch_footprints(const wproj_kernels *k, int64_t nvis, const double *uvw,
+                             const void *wt, int32_t *out, hipStream_t s) {
+  if (nvis == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((nvis + 255) / 256);
+  if (k->params.precision == WPROJ_F64)
+    hipLaunchKernelGGL(footprint_kernel<double>, dim3(blocks), dim3(256), 0, s, k->geo, nvis, uvw,
+                       (const double *)wt, out);
+  else
+    hipLaunchKernelGGL(footprint_kernel<float>, dim3(blocks), dim3(256), 0, s, k->geo, nvis, uvw,
+                       (const float *)wt, out);
+  return hipGetLastError();
+}
+
 }  // namespace wproj

@@ -97,20 +97,24 @@ __global__ void __launch_bounds__(64)
   }
 }
 
-// dst row k <- src row perm[k], rows of `words` 32-bit words; one workgroup per row.
+// dst row k <- src row perm[k], rows of `words` elements of type V (4 or 16 bytes); each
+// wavefront copies one row at a time.
+template <typename V>
 __global__ void __launch_bounds__(256)
     gather_rows_kernel(int64_t n_rows, int64_t words, const int64_t *__restrict__ perm,
-                       int64_t n_src_rows, const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,
+                       int64_t n_src_rows, const V *__restrict__ src, V *__restrict__ dst,
                        unsigned long long *bad) {
-  for (int64_t k = blockIdx.x; k < n_rows; k += gridDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); k < n_rows; k += waves) {
     const int64_t p = perm[k];
     if (p < 0 || p >= n_src_rows) {
-      if (bad && threadIdx.x == 0) atomicAdd(bad, 1ull);
+      if (bad && lane == 0) atomicAdd(bad, 1ull);
       continue;
     }
-    const uint32_t *s = src + p * words;
-    uint32_t *d = dst + k * words;
-    for (int64_t i = threadIdx.x; i < words; i += blockDim.x) d[i] = s[i];
+    const V *s = src + p * words;
+    V *d = dst + k * words;
+    for (int64_t i = lane; i < words; i += 64) d[i] = s[i];
   }
 }
 
@@ -162,10 +166,17 @@ hipError_t launch_gather_rows(int64_t n_rows, int64_t row_bytes, const int64_t *
                               int64_t n_src_rows, const void *src, void *dst, int64_t *bad,
                               hipStream_t s) {
   if (n_rows == 0) return hipSuccess;
-  const unsigned blocks = (unsigned)std::min<int64_t>(n_rows, 1 << 20);
-  hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks), dim3(256), 0, s, n_rows, row_bytes / 4, perm,
-                     n_src_rows, (const uint32_t *)src, (uint32_t *)dst,
-                     reinterpret_cast<unsigned long long *>(bad));
+  const unsigned blocks = (unsigned)std::min<int64_t>((n_rows + 3) / 4, 1 << 16);
+  auto *b = reinterpret_cast<unsigned long long *>(bad);
+  // 16-byte moves when rows and both buffers allow them
+  if (row_bytes % 16 == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0 &&
+      (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+    hipLaunchKernelGGL(gather_rows_kernel<uint4>, dim3(blocks), dim3(256), 0, s, n_rows, row_bytes / 16,
+                       perm, n_src_rows, (const uint4 *)src, (uint4 *)dst, b);
+  } else {
+    hipLaunchKernelGGL(gather_rows_kernel<uint32_t>, dim3(blocks), dim3(256), 0, s, n_rows, row_bytes / 4,
+                       perm, n_src_rows, (const uint32_t *)src, (uint32_t *)dst, b);
+  }
   return hipGetLastError();
 }
 

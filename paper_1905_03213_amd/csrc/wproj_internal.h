@@ -178,6 +178,9 @@ hipError_t launch_plain_grid(const wproj_kernels *k, int64_t nvis, const double 
 hipError_t launch_plain_degrid(const wproj_kernels *k, int64_t nvis, const double *uvw,
                                const void *grid, const int64_t *img_off, void *vis_out,
                                hipStream_t s);
+// Per-visibility footprint and class (wproj_footprints).
+hipError_t launch_footprints(const wproj_kernels *k, int64_t nvis, const double *uvw,
+                             const void *wt, int32_t *out, hipStream_t s);
 
 // Image-plane kernels around the FFTs.
 hipError_t launch_g2i_correct(const wproj_kernels *k, const void *fgrid, void *image,

@@ -208,6 +208,18 @@ def image(k: Kernels, direction: int, grid_buf: torch.Tensor, image_buf: torch.T
         _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
 
 
+def footprints(k: Kernels, uvw: torch.Tensor, weight: Optional[torch.Tensor] = None,
+               stream=None) -> torch.Tensor:
+    """wproj_footprints: int32 [nvis, 6] = (x0, y0, ou, ov, p, class) per visibility."""
+    nvis = int(uvw.shape[0])
+    out = torch.empty((nvis, 6), dtype=torch.int32, device=uvw.device)
+    _lib.check("wproj_footprints", _lib.lib().wproj_footprints(
+        k.handle, nvis, _ptr(uvw, "uvw", torch.float64, 3 * nvis),
+        _ptr(weight, "weight", k.real, nvis), _ptr(out, "out", torch.int32, 6 * nvis),
+        _stream(stream)))
+    return out
+
+
 def regroup_rows(ant1: torch.Tensor, ant2: torch.Tensor, n_ant: int, stream=None):
     """wproj_regroup_rows (Eqs. 5 and 6): returns (perm, start, counts), int64 device tensors;
     rows in increasing baseline number, time order kept inside each baseline."""

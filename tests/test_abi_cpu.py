@@ -70,6 +70,7 @@ def test_null_handle_paths():
     assert L.wproj_degrid(None, 0, None, None, None, None, None, 0, None) == -1
     assert L.wproj_image(None, 0, None, None, None, None, 0, None) == -1
     assert L.wproj_export(None, 0, None, 0, None, None) == -1
+    assert L.wproj_footprints(None, 0, None, None, None, None) == -1
     assert L.wproj_free_kernels(None) == 0
 
 

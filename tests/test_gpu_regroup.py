@@ -99,6 +99,8 @@ def test_gather_rows_matches_indexing():
     vis = torch.randn((n_rows, 16), dtype=torch.complex64, generator=g).cuda()
     assert torch.equal(W.gather_rows(perm, uvw), uvw[perm])
     assert torch.equal(W.gather_rows(perm, vis), vis[perm])
+    wt3 = torch.randn((n_rows, 3), dtype=torch.float32, generator=g).cuda()  # 12-byte rows
+    assert torch.equal(W.gather_rows(perm, wt3), wt3[perm])
     # out-of-range entries leave their rows untouched and are counted
     bad_perm = perm.clone()
     bad_perm[5] = -1
