@@ -278,6 +278,54 @@ def grid(plan: Plan, tables, uvw, vis, weight, image_offsets=None):
 # ---------------------------------------------------------------------------
 
 
+def grid_cells(plan: Plan, tables, uvw, vis, weight):
+    """O5 for one image, kept sparse: the touched cells as (flat index y N + x, value).
+
+    Same contributions as grid() (W V T_p[ov][ou][kv][ku] at cell (y0 + kv, x0 + ku)),
+    summed per cell; for grids too large to hold densely on the host.
+    Returns (cells int64 sorted, values complex128, sumW, counters[3]).
+    """
+    uvw = np.asarray(uvw, dtype=np.float64)
+    wv = np.asarray(weight, dtype=np.float64) * np.asarray(vis, dtype=np.complex128)
+    geo = snap(plan, uvw, weight)
+    val = geo["valid"]
+    idx, con = [], []
+    for p in np.unique(geo["p"][val]):
+        sel = val & (geo["p"] == p)
+        T = tables[p]
+        S = T.shape[-1]
+        x0, y0 = geo["x0"][sel], geo["y0"][sel]
+        ou, ov = geo["ou"][sel], geo["ov"][sel]
+        a = wv[sel]
+        for kv in range(S):
+            for ku in range(S):
+                idx.append((y0 + kv) * plan.n + (x0 + ku))
+                con.append(a * T[ov, ou, kv, ku])
+    if not idx:
+        return (np.zeros(0, np.int64), np.zeros(0, np.complex128),
+                float(np.asarray(weight)[val].sum()), geo["counters"])
+    idx = np.concatenate(idx)
+    con = np.concatenate(con)
+    cells, inv = np.unique(idx, return_inverse=True)
+    vals = np.zeros(cells.shape[0], dtype=np.complex128)
+    np.add.at(vals, inv, con)
+    return cells, vals, float(np.asarray(weight, dtype=np.float64)[val].sum()), geo["counters"]
+
+
+def image_pixels(plan: Plan, cells, vals, sumw, ys, xs):
+    """O6 + O7 at chosen pixels, from a sparse grid: kappa(x) kappa(y) Re(sum over cells of
+    G[Y][X] exp(+2 pi i ((X - N/2)(x - N/2) + (Y - N/2)(y - N/2))/N)) / sumW."""
+    n = plan.n
+    k = kappa(plan)
+    Y = (np.asarray(cells) // n - n // 2).astype(np.float64)
+    X = (np.asarray(cells) % n - n // 2).astype(np.float64)
+    out = np.empty(len(ys))
+    for i, (y, x) in enumerate(zip(ys, xs)):
+        ph = 2.0 * np.pi * (X * (x - n // 2) + Y * (y - n // 2)) / n
+        out[i] = np.sum(vals * np.exp(1j * ph)).real * k[x] * k[y] / sumw
+    return out
+
+
 def centred_idft(grid2d: np.ndarray) -> np.ndarray:
     """O6: out[y][x] = sum_{Y,X} G[Y][X] exp(+2 pi i ((X-N/2)(x-N/2) + (Y-N/2)(y-N/2))/N)."""
     n = grid2d.shape[-1]

@@ -428,3 +428,28 @@ def test_eq6_scan_and_regroup_match_brute_force():
     assert s.tolist() == [int(c[:k].sum()) for k in range(40)]
     perm = eq56.regroup_order(b, 40)
     assert (perm == np.argsort(b, kind="stable")).all()
+
+
+# --------------------------------------------------------------------------- sparse forms
+def test_sparse_grid_and_pixel_image_match_dense_forms():
+    """grid_cells (the touched cells only, for grids too large for the host) holds exactly
+    the dense grid's non-zero cells; image_pixels (a direct sum per pixel) matches the
+    FFT-based image on the inner half (the edge kappa^2 ~1e7 amplifies FFT rounding)."""
+    wl = synth.cfg1()
+    plan = R.Plan(wl.params)
+    tabs = R.kernel_tables(plan)
+    uvw, vis, wt = (np.asarray(a) for a in (wl.uvw, wl.vis, wl.weight))
+    G, sw, c = R.grid(plan, tabs, uvw, vis, wt)
+    cells, vals, sw2, c2 = R.grid_cells(plan, tabs, uvw, vis, wt)
+    dense = np.zeros(plan.n * plan.n, dtype=np.complex128)
+    dense[cells] = vals
+    assert np.array_equal(dense, G[0].ravel())
+    assert np.count_nonzero(G[0]) == np.count_nonzero(vals)
+    assert sw2 == sw[0] and c2.tolist() == c.tolist()
+    img = R.grid_to_image(plan, G, sw)[0]
+    rng = np.random.default_rng(0)
+    n = plan.n
+    ys = rng.integers(n // 4, 3 * n // 4, 40)
+    xs = rng.integers(n // 4, 3 * n // 4, 40)
+    pix = R.image_pixels(plan, cells, vals, sw2, ys, xs)
+    assert np.abs(pix - img[ys, xs]).max() <= 1e-14 * np.abs(img).max()
