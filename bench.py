@@ -199,6 +199,25 @@ def main():
     k.profile(False)
     degrid_ms = dph["degrid"][0] / max(dph["degrid"][1], 1)
 
+    # a plan: the binning kept, then gridding / degridding of new visibilities on the same
+    # rows (an imaging loop's major cycles)
+    plan = W.Plan(k, uvw, wt32)
+    plan.grid(vis32, g)
+    torch.cuda.synchronize()
+    k.profile(True)
+    k.profile_read()
+    for _ in range(reps):
+        g.zero_()
+        plan.grid(vis32, g)
+    for _ in range(reps):
+        plan.degrid(g, vout)
+    torch.cuda.synchronize()
+    pph = k.profile_read()
+    k.profile(False)
+    plan.free()
+    planned_grid_ms = sum(pph[ph][0] / max(pph[ph][1], 1) for ph in ("grid", "reduce"))
+    planned_degrid_ms = pph["degrid"][0] / max(pph["degrid"][1], 1)
+
     # rows regrouped by baseline (Eqs. 5 and 6) and the rows of uvw and visibilities
     # gathered into that order: the paper's GPU-side data preparation, on the same rows
     src = wl.sources
@@ -230,6 +249,8 @@ def main():
     del uvw_out, vis_out, perm, a1, a2
 
     extra = {"phases_ms": per, "degrid": {"ms": degrid_ms, "mvis_per_s": n_valid / degrid_ms / 1e3},
+             "planned": {"grid_ms": planned_grid_ms, "grid_mvis_per_s": n_valid / planned_grid_ms / 1e3,
+                         "degrid_ms": planned_degrid_ms},
              "regroup_by_baseline": {"rows": n_t * n_bl, "ms": regroup_ms,
                                      "gather_uvw_vis_ms": gather_ms,
                                      "gather_gb_per_s": gather_bytes / gather_ms / 1e6},

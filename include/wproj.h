@@ -89,6 +89,7 @@ typedef struct {
 } wproj_params;
 
 typedef struct wproj_kernels wproj_kernels; /* opaque handle */
+typedef struct wproj_plan wproj_plan;       /* opaque: a kept binning (see wproj_plan_create) */
 
 /*
  * Build the oversampled w-kernel tables on the device, in FP64, then store
@@ -236,6 +237,34 @@ typedef enum {
  */
 int wproj_profile(wproj_kernels *k, int enable);
 int wproj_profile_read(wproj_kernels *k, double *ms, int64_t *count);
+
+/*
+ * Plans: the binning of one set of rows, kept for repeated gridding and degridding of
+ * those rows (e.g. the major cycles of an imaging loop, where uvw and weights stay fixed
+ * and the visibilities change).  wproj_plan_create bins nvis rows as wproj_grid does
+ * (same footprints, same drops and counters; weight_sum and counters are accumulated
+ * into here, nullable) and keeps, for every gridded row, its footprint, sub-kernel,
+ * weight and row index in the caller's workspace.  Then
+ *   wproj_grid_planned(plan, vis, grid)       == wproj_grid with the plan's uvw, weights
+ *                                                and image offsets, accumulated into grid
+ *                                                (no weight_sum or counters);
+ *   wproj_degrid_planned(plan, model, vis_out) == wproj_degrid of the rows the plan grids;
+ *                                                rows it does not grid (flagged, bad weight,
+ *                                                dropped) get 0.
+ * The workspace (at least wproj_workspace_size(k, nvis) bytes) belongs to the plan until
+ * wproj_plan_free: it must stay allocated and must not be passed to other calls.  Calls
+ * on one plan must not run concurrently (they share the workspace's scratch part); the
+ * handle must outlive the plan, and its tuning at creation time is kept by the plan.
+ * vis / vis_out: [nvis] complex of the handle's precision; grids as for wproj_grid.
+ * Only the binned (tiled) algorithm builds plans (WPROJ_EUNSUPPORTED otherwise).
+ * Errors: WPROJ_EINVAL, WPROJ_EUNSUPPORTED, WPROJ_EWORKSPACE, WPROJ_ENOMEM, WPROJ_EHIP.
+ */
+int wproj_plan_create(const wproj_kernels *k, int64_t nvis, const double *uvw, const void *weight,
+                      const int64_t *image_offsets, double *weight_sum, int64_t *counters,
+                      void *workspace, int64_t workspace_bytes, void *stream, wproj_plan **out);
+int wproj_plan_free(wproj_plan *plan);
+int wproj_grid_planned(const wproj_plan *plan, const void *vis, void *grid, void *stream);
+int wproj_degrid_planned(const wproj_plan *plan, const void *model_grid, void *vis_out, void *stream);
 
 /*
  * Per-visibility footprint: the uvw -> grid step every gridding and degridding call

@@ -14,6 +14,7 @@ from .wproj import (  # noqa: F401
     GRID_TO_IMAGE_RAW,
     IMAGE_TO_GRID,
     Kernels,
+    Plan,
     WprojError,
     autotune,
     degrid,

@@ -22,7 +22,8 @@ EXPORTED = ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_w
             "wproj_grid", "wproj_degrid", "wproj_image", "wproj_autotune", "wproj_tuning",
             "wproj_profile", "wproj_profile_read", "wproj_last_error", "wproj_version",
             "wproj_footprints", "wproj_regroup_workspace_size", "wproj_regroup_rows",
-            "wproj_gather_rows")
+            "wproj_gather_rows", "wproj_plan_create", "wproj_plan_free", "wproj_grid_planned",
+            "wproj_degrid_planned")
 PHASES = ("bin", "grid", "plain", "fft", "correct", "degrid", "reduce")
 
 
@@ -80,6 +81,10 @@ def lib():
     L.wproj_last_error.argtypes = []
     L.wproj_version.argtypes = []
     L.wproj_footprints.argtypes = [vp, i64, vp, vp, vp, vp]
+    L.wproj_plan_create.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, i64, vp, ctypes.POINTER(vp)]
+    L.wproj_plan_free.argtypes = [vp]
+    L.wproj_grid_planned.argtypes = [vp, vp, vp, vp]
+    L.wproj_degrid_planned.argtypes = [vp, vp, vp, vp]
     L.wproj_regroup_workspace_size.argtypes = [i64, ctypes.c_int32]
     L.wproj_regroup_workspace_size.restype = i64
     L.wproj_regroup_rows.argtypes = [i64, vp, vp, ctypes.c_int32, vp, vp, vp, vp, i64, vp]
@@ -87,7 +92,8 @@ def lib():
     for name in ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_grid",
                  "wproj_degrid", "wproj_image", "wproj_autotune", "wproj_tuning", "wproj_profile",
                  "wproj_profile_read", "wproj_version", "wproj_footprints", "wproj_regroup_rows",
-                 "wproj_gather_rows"):
+                 "wproj_gather_rows", "wproj_plan_create", "wproj_plan_free", "wproj_grid_planned",
+                 "wproj_degrid_planned"):
         getattr(L, name).restype = i32
     _lib = L
     return L

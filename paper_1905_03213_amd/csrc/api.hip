@@ -734,6 +734,97 @@ int wproj_image(const wproj_kernels *k, int direction, void *grid, void *image,
 
 }  // extern "C"
 
+// A binning kept for repeated gridding / degridding of the same rows.
+struct wproj_plan {
+  const wproj_kernels *k;
+  int64_t nvis;
+  wproj::BinShape B;
+  wproj::BinWorkspace W;
+};
+
+int wproj_plan_create(const wproj_kernels *k, int64_t nvis, const double *uvw, const void *weight,
+                      const int64_t *image_offsets, double *weight_sum, int64_t *counters,
+                      void *workspace, int64_t workspace_bytes, void *stream, wproj_plan **out) {
+  g_err.clear();
+  if (!out) return fail(WPROJ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!k) return fail(WPROJ_EINVAL, "handle is NULL");
+  if (nvis < 0) return fail(WPROJ_EINVAL, "nvis < 0");
+  if (nvis > 0 && !uvw) return fail(WPROJ_EINVAL, "uvw is required");
+  if (k->params.n_images > 1 && !image_offsets)
+    return fail(WPROJ_EINVAL, "image_offsets is required when n_images > 1");
+  if (k->params.algorithm != WPROJ_ALGO_TILED)
+    return fail(WPROJ_EUNSUPPORTED, "plans are built by the binned (tiled) algorithm only");
+  int rc = check_device(k);
+  if (rc != WPROJ_OK) return rc;
+  const int64_t need = workspace_bytes_for(k, nvis);
+  if (workspace_bytes < need || (need > 0 && !workspace))
+    return fail(WPROJ_EWORKSPACE, "workspace of %lld bytes given, %lld needed",
+                (long long)workspace_bytes, (long long)need);
+  if (nvis > 0xfffffffell) return fail(WPROJ_EINVAL, "a plan holds at most 2^32 - 2 visibilities");
+  if (k->n_taps > (int64_t)kTapMask)
+    return fail(WPROJ_EUNSUPPORTED, "kernel tables of %lld taps exceed the tiled path's 2^26",
+                (long long)k->n_taps);
+  auto *p = new (std::nothrow) wproj_plan;
+  if (!p) return fail(WPROJ_ENOMEM, "plan allocation failed");
+  p->k = k;
+  p->nvis = nvis;
+  p->B = bin_shape(k);
+  if (p->B.n_keys >= (int64_t)0xffffffffll) {
+    const long long n_keys = (long long)p->B.n_keys;
+    delete p;
+    return fail(WPROJ_EUNSUPPORTED, "%lld bins exceed the tiled path's 32-bit keys", n_keys);
+  }
+  carve(k, nvis, (char *)workspace, p->W);
+  if (nvis > 0) {
+    PhaseTimer pt(k, WPROJ_PHASE_BIN, (hipStream_t)stream);
+    const hipError_t e = launch_bin(k, p->B, nvis, uvw, nullptr, weight, image_offsets, weight_sum,
+                                    counters, p->W, (hipStream_t)stream);
+    if (e != hipSuccess) {
+      delete p;
+      return fail(WPROJ_EHIP, "binning: %s", hipGetErrorString(e));
+    }
+  }
+  *out = p;
+  return WPROJ_OK;
+}
+
+int wproj_plan_free(wproj_plan *p) {
+  g_err.clear();
+  delete p;
+  return WPROJ_OK;
+}
+
+int wproj_grid_planned(const wproj_plan *p, const void *vis, void *grid, void *stream) {
+  g_err.clear();
+  if (!p) return fail(WPROJ_EINVAL, "plan is NULL");
+  if (!grid) return fail(WPROJ_EINVAL, "grid is NULL");
+  if (p->nvis > 0 && !vis) return fail(WPROJ_EINVAL, "vis is required");
+  int rc = check_device(p->k);
+  if (rc != WPROJ_OK) return rc;
+  if (p->nvis == 0) return WPROJ_OK;
+  hipStream_t s = (hipStream_t)stream;
+  {
+    PhaseTimer pt(p->k, WPROJ_PHASE_GRID, s);
+    HIP_TRY(launch_tiled_grid(p->k, p->B, p->W, grid, s, vis));
+  }
+  PhaseTimer pt(p->k, WPROJ_PHASE_REDUCE, s);
+  HIP_TRY(launch_tile_reduce(p->k, p->B, p->W, grid, s));
+  return WPROJ_OK;
+}
+
+int wproj_degrid_planned(const wproj_plan *p, const void *model_grid, void *vis_out, void *stream) {
+  g_err.clear();
+  if (!p) return fail(WPROJ_EINVAL, "plan is NULL");
+  if (p->nvis > 0 && (!model_grid || !vis_out)) return fail(WPROJ_EINVAL, "model_grid and vis_out are required");
+  int rc = check_device(p->k);
+  if (rc != WPROJ_OK) return rc;
+  if (p->nvis == 0) return WPROJ_OK;
+  PhaseTimer pt(p->k, WPROJ_PHASE_DEGRID, (hipStream_t)stream);
+  HIP_TRY(launch_tiled_degrid(p->k, p->B, p->W, model_grid, vis_out, p->nvis, (hipStream_t)stream));
+  return WPROJ_OK;
+}
+
 int wproj_footprints(const wproj_kernels *k, int64_t nvis, const double *uvw, const void *weight,
                      int32_t *out, void *stream) {
   g_err.clear();

@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(256)
     r.wr = w * v.x;
     r.wi = w * v.y;
   } else {
-    set_row(r, (uint32_t)j);
+    set_plan(r, w, (uint32_t)j);
   }
   rec[offset[key] + slots[j]] = r;
 }

@@ -90,6 +90,15 @@ template <> struct Cx<double> { using T = double2; };
 constexpr int kGroup = 8;
 constexpr int kMaxWavesPerBlock = 4;
 
+// A row-carrying record (weight, row) turned into W V from the visibility it names.
+template <typename Rec, typename C2>
+__device__ inline void to_weighted(Rec &r, const C2 *vis) {
+  const C2 v = vis[get_row(r)];
+  const auto wgt = r.wr;
+  r.wr = wgt * v.x;
+  r.wi = wgt * v.y;
+}
+
 // One record's read-add-write of its 64-cell footprint (lane = tap) in the private tile.
 template <typename C2, typename Real, typename Tap>
 __device__ inline void accumulate(C2 *acc, int a, Real wr, Real wi, const Tap &t) {
@@ -101,14 +110,16 @@ __device__ inline void accumulate(C2 *acc, int a, Real wr, Real wi, const Tap &t
   acc[a] = v;
 }
 
-// S = fixed support (0 = per-record support).
-template <typename Real, typename Rec, typename Tab, int S>
+// S = fixed support (0 = per-record support).  PLANNED: the records are row-carrying
+// (weight, row) and W V is formed from vis[row] as each record is loaded.
+template <typename Real, typename Rec, typename Tab, int S, bool PLANNED>
 __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
     tiled_grid_kernel(Geometry G, BinShape B, int pitch, int rows, int wave_lds,
                       const Tab *__restrict__ tab, uint32_t tab_bytes,
                       const Rec *__restrict__ rec, const WorkItem *__restrict__ items,
                       const uint32_t *__restrict__ n_items_ptr, uint32_t *counter,
-                      typename Cx<Real>::T *__restrict__ partial) {
+                      typename Cx<Real>::T *__restrict__ partial,
+                      const typename Cx<Real>::T *__restrict__ vis) {
   using C2 = typename Cx<Real>::T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = threadIdx.x & 63;
@@ -138,6 +149,7 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
       const uint32_t i = b + (uint32_t)lane;
       if (i < n_rec) {
         dst = rec[w.begin + i];
+        if constexpr (PLANNED) to_weighted(dst, vis);
       } else {  // padding records carry zero weight
         dst.lds = 0;
         dst.tap = 0;
@@ -183,7 +195,8 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
       // General path (per-record support up to 32): records by wave-uniform loads, each
       // record's taps in passes of 64 lanes.
       for (uint32_t r = w.begin; r < w.end; ++r) {
-        const Rec rr = rec[r];
+        Rec rr = rec[r];
+        if constexpr (PLANNED) to_weighted(rr, vis);
         const uint32_t tp = rr.tap;
         const int Sr = S > 0 ? S : (int)(tp >> kTapBits) + 1;
         const uint32_t tb = tp & kTapMask;
@@ -242,10 +255,10 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-template <typename Real, typename Rec, typename Tab, int S>
+template <typename Real, typename Rec, typename Tab, int S, bool PLANNED>
 hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
-                      const BinWorkspace &W, void *grid, hipStream_t s) {
-  auto kern = tiled_grid_kernel<Real, Rec, Tab, S>;
+                      const BinWorkspace &W, void *grid, const void *vis, hipStream_t s) {
+  auto kern = tiled_grid_kernel<Real, Rec, Tab, S, PLANNED>;
   // as many wavefronts per workgroup (up to 4) as their private tiles fit in LDS
   const int wpb = (int)std::max<size_t>(1, std::min<size_t>(kMaxWavesPerBlock, k->max_lds / ts.lds_bytes));
   const size_t lds = ts.lds_bytes * wpb;
@@ -261,7 +274,7 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, s, k->geo, B, ts.pitch,
                      ts.rows, wave_lds, (const Tab *)k->d_tab, (uint32_t)(k->n_taps * sizeof(Tab)),
                      (const Rec *)W.rec, W.items, W.choff + B.n_tiles, W.counter,
-                     (typename Cx<Real>::T *)W.partial);
+                     (typename Cx<Real>::T *)W.partial, (const typename Cx<Real>::T *)vis);
   return hipGetLastError();
 }
 
@@ -275,12 +288,21 @@ hipError_t launch_reduce(const wproj_kernels *k, const BinShape &B, const TileSh
   return hipGetLastError();
 }
 
-template <typename Real, typename Rec, typename Tab>
+template <typename Real, typename Rec, typename Tab, bool PLANNED>
 hipError_t dispatch_support(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
-                            const BinWorkspace &W, void *grid, hipStream_t s) {
-  if (k->uniform_support && k->s_max == 8) return launch_one<Real, Rec, Tab, 8>(k, B, ts, W, grid, s);
-  if (k->uniform_support && k->s_max == 7) return launch_one<Real, Rec, Tab, 7>(k, B, ts, W, grid, s);
-  return launch_one<Real, Rec, Tab, 0>(k, B, ts, W, grid, s);
+                            const BinWorkspace &W, void *grid, const void *vis, hipStream_t s) {
+  if (k->uniform_support && k->s_max == 8)
+    return launch_one<Real, Rec, Tab, 8, PLANNED>(k, B, ts, W, grid, vis, s);
+  if (k->uniform_support && k->s_max == 7)
+    return launch_one<Real, Rec, Tab, 7, PLANNED>(k, B, ts, W, grid, vis, s);
+  return launch_one<Real, Rec, Tab, 0, PLANNED>(k, B, ts, W, grid, vis, s);
+}
+
+template <typename Real, typename Rec, typename Tab>
+hipError_t dispatch_planned(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
+                            const BinWorkspace &W, void *grid, const void *vis, hipStream_t s) {
+  return vis ? dispatch_support<Real, Rec, Tab, true>(k, B, ts, W, grid, vis, s)
+             : dispatch_support<Real, Rec, Tab, false>(k, B, ts, W, grid, vis, s);
 }
 
 }  // namespace
@@ -301,17 +323,17 @@ TileShape tile_shape(const wproj_kernels *k, int tile) {
 }
 
 hipError_t launch_tiled_grid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
-                             void *grid, hipStream_t s) {
+                             void *grid, hipStream_t s, const void *vis) {
   const TileShape ts = tile_shape(k, B.tile);
   hipError_t e = launch_fill_u32(W.counter, 1, 0u, s);
   if (e != hipSuccess) return e;
   switch (k->params.precision) {
     case WPROJ_F64:
-      return dispatch_support<double, RecordF64, double2>(k, B, ts, W, grid, s);
+      return dispatch_planned<double, RecordF64, double2>(k, B, ts, W, grid, vis, s);
     case WPROJ_F32:
-      return dispatch_support<float, RecordF32, float2>(k, B, ts, W, grid, s);
+      return dispatch_planned<float, RecordF32, float2>(k, B, ts, W, grid, vis, s);
     default:
-      return dispatch_support<float, RecordF32, half2c>(k, B, ts, W, grid, s);
+      return dispatch_planned<float, RecordF32, half2c>(k, B, ts, W, grid, vis, s);
   }
 }
 

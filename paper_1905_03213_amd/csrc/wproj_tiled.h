@@ -27,24 +27,25 @@ struct RecordF64 {
   double wr, wi;
 };
 
-// Degridding records carry the output row instead of W V, in the bits of `wr`.
-__host__ __device__ inline void set_row(RecordF32 &r, uint32_t j) {
-  __builtin_memcpy(&r.wr, &j, 4);
-  r.wi = 0.0f;
+// Row-carrying records (degridding and planned gridding) hold the visibility's weight in
+// `wr` and its row in the low 32 bits of `wi` instead of W V.
+__host__ __device__ inline void set_plan(RecordF32 &r, float w, uint32_t j) {
+  r.wr = w;
+  __builtin_memcpy(&r.wi, &j, 4);
 }
-__host__ __device__ inline void set_row(RecordF64 &r, uint32_t j) {
-  r.wr = 0.0;
-  __builtin_memcpy(&r.wr, &j, 4);
+__host__ __device__ inline void set_plan(RecordF64 &r, double w, uint32_t j) {
+  r.wr = w;
   r.wi = 0.0;
+  __builtin_memcpy(&r.wi, &j, 4);
 }
 __host__ __device__ inline uint32_t get_row(const RecordF32 &r) {
   uint32_t j;
-  __builtin_memcpy(&j, &r.wr, 4);
+  __builtin_memcpy(&j, &r.wi, 4);
   return j;
 }
 __host__ __device__ inline uint32_t get_row(const RecordF64 &r) {
   uint32_t j;
-  __builtin_memcpy(&j, &r.wr, 4);
+  __builtin_memcpy(&j, &r.wi, 4);
   return j;
 }
 
@@ -87,8 +88,9 @@ int64_t scan_temp_words(int64_t n);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
                                  hipStream_t s);
-// Bins visibilities for gridding (records carry W V) or, with vis == nullptr and
-// wt == nullptr, for degridding (records carry the visibility's row; weights taken as 1).
+// Bins visibilities for gridding (records carry W V) or, with vis == nullptr, into
+// row-carrying records (weight and row: degridding, with wt == nullptr and weights taken
+// as 1, and planned gridding).
 hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, const double *uvw,
                       const void *vis, const void *wt, const int64_t *img_off, double *wsum,
                       int64_t *counters, const BinWorkspace &W, hipStream_t s);
@@ -102,8 +104,9 @@ struct TileShape {
 };
 TileShape tile_shape(const wproj_kernels *k, int tile);
 // The tile gridder into the work items' partial tiles, then their sum into the grid.
+// With vis != nullptr the records are row-carrying (a plan) and W V is formed from vis.
 hipError_t launch_tiled_grid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
-                             void *grid, hipStream_t s);
+                             void *grid, hipStream_t s, const void *vis = nullptr);
 hipError_t launch_tile_reduce(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
                               void *grid, hipStream_t s);
 hipError_t launch_tiled_degrid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,

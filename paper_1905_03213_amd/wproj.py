@@ -208,6 +208,48 @@ def image(k: Kernels, direction: int, grid_buf: torch.Tensor, image_buf: torch.T
         _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
 
 
+class Plan:
+    """wproj_plan_create: the binning of one set of rows kept for repeated gridding and
+    degridding.  Holds its workspace; free() releases the plan."""
+
+    def __init__(self, k: Kernels, uvw: torch.Tensor, weight: torch.Tensor,
+                 image_offsets: Optional[torch.Tensor] = None,
+                 weight_sum: Optional[torch.Tensor] = None, counters: Optional[torch.Tensor] = None,
+                 stream=None):
+        self.k = k
+        self.nvis = int(uvw.shape[0])
+        ni = k.params.get("n_images", 1)
+        self.workspace = k.workspace(self.nvis, device=uvw.device)
+        h = ctypes.c_void_p()
+        _lib.check("wproj_plan_create", _lib.lib().wproj_plan_create(
+            k.handle, self.nvis, _ptr(uvw, "uvw", torch.float64, 3 * self.nvis),
+            _ptr(weight, "weight", k.real, self.nvis),
+            _ptr(image_offsets, "image_offsets", torch.int64, ni + 1),
+            _ptr(weight_sum, "weight_sum", torch.float64, ni),
+            _ptr(counters, "counters", torch.int64, 3),
+            _ptr(self.workspace, "workspace", torch.uint8), self.workspace.numel(),
+            _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def grid(self, vis: torch.Tensor, grid_buf: torch.Tensor, stream=None):
+        n, ni = self.k.params["n"], self.k.params.get("n_images", 1)
+        _lib.check("wproj_grid_planned", _lib.lib().wproj_grid_planned(
+            self.handle, _ptr(vis, "vis", self.k.cplx, self.nvis),
+            _ptr(grid_buf, "grid", self.k.cplx, ni * n * n), _stream(stream)))
+
+    def degrid(self, model_grid: torch.Tensor, vis_out: torch.Tensor, stream=None):
+        n, ni = self.k.params["n"], self.k.params.get("n_images", 1)
+        _lib.check("wproj_degrid_planned", _lib.lib().wproj_degrid_planned(
+            self.handle, _ptr(model_grid, "model_grid", self.k.cplx, ni * n * n),
+            _ptr(vis_out, "vis_out", self.k.cplx, self.nvis), _stream(stream)))
+
+    def free(self):
+        if self.handle is not None and self.handle.value:
+            _lib.lib().wproj_plan_free(self.handle)
+        self.handle = None
+        self.workspace = None
+
+
 def footprints(k: Kernels, uvw: torch.Tensor, weight: Optional[torch.Tensor] = None,
                stream=None) -> torch.Tensor:
     """wproj_footprints: int32 [nvis, 6] = (x0, y0, ou, ov, p, class) per visibility."""

@@ -71,6 +71,13 @@ def test_null_handle_paths():
     assert L.wproj_image(None, 0, None, None, None, None, 0, None) == -1
     assert L.wproj_export(None, 0, None, 0, None, None) == -1
     assert L.wproj_footprints(None, 0, None, None, None, None) == -1
+    out = ctypes.c_void_p(5)
+    assert L.wproj_plan_create(None, 0, None, None, None, None, None, None, 0, None,
+                               ctypes.byref(out)) == -1
+    assert out.value is None  # cleared on failure
+    assert L.wproj_grid_planned(None, None, None, None) == -1
+    assert L.wproj_degrid_planned(None, None, None, None) == -1
+    assert L.wproj_plan_free(None) == 0
     assert L.wproj_free_kernels(None) == 0
 
 
