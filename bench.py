@@ -311,6 +311,34 @@ def main():
         del g64, ws64
         k64.free()
 
+    if not args.no_fp64:
+        # FP32 accumulation with FP16 kernel tables (half the table bytes the gridder fetches)
+        kh = W.make_kernels({**params, "precision": "f32_f16table", "tile": 0, "chunk": 0})
+        gh = kh.new_grid()
+        wsh = kh.workspace(nvis)
+        th = W.autotune(kh, uvw, vis32, wt32, workspace=wsh)
+        swh = torch.zeros(1, dtype=torch.float64, device=dev)
+
+        def step_h():
+            gh.zero_()
+            swh.zero_()
+            W.grid(kh, uvw, vis32, wt32, gh, weight_sum=swh, workspace=wsh)
+            W.image(kh, W.GRID_TO_IMAGE, gh, img, swh, workspace=wsh)
+
+        step_h()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            step_h()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        msh = ev0.elapsed_time(ev1) / args.steps
+        extra["f32_f16table"] = {"ms_per_step": msh, "mvis_per_s": n_valid / msh / 1e3,
+                                 "tuning": {"tile": th[0], "chunk": th[1]}}
+        log(f"fp32 with fp16 tables: {msh:.3f} ms/step, {n_valid / msh / 1e3:.1f} Mvis/s")
+        del gh, wsh
+        kh.free()
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(wl, args.cpu_seconds)

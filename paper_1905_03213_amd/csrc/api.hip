@@ -220,7 +220,9 @@ BinShape bin_shape(const wproj_kernels *k) {
 int64_t carve(const wproj_kernels *k, int64_t nvis, char *base, BinWorkspace &W) {
   const BinShape B = bin_shape(k);
   const int64_t rec_bytes = k->params.precision == WPROJ_F64 ? sizeof(RecordF64) : sizeof(RecordF32);
-  const int64_t max_items = B.n_tiles + nvis / B.chunk + 1;
+  // a tile with r records gives ceil(r / chunk) <= r / chunk + 1 items, and at most
+  // min(n_tiles, nvis) tiles hold records
+  const int64_t max_items = std::min<int64_t>(B.n_tiles, nvis) + nvis / B.chunk + 1;
   int64_t off = 0;
   auto take = [&](int64_t bytes) {
     char *p = base ? base + off : nullptr;
