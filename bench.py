@@ -59,6 +59,10 @@ def parse():
                     help="also time the step replayed from a captured HIP graph")
     ap.add_argument("--tile", type=int, default=0, help="fix the tile side (skips autotuning)")
     ap.add_argument("--chunk", type=int, default=0, help="fix the work-item length (with --tile)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only sweep the binned gridding call over full support 3..16 (2048^2) and "
+                         "image size 128..4096 (support 8) at a fixed 1e-5 rad cell, FP32 and FP64, "
+                         "on the benchmark's visibilities; one JSON line per point")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB device buffer 4 times (a kernel of known traffic "
                          "for scaling hardware byte counters) and exit")
@@ -87,6 +91,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": a.numel() * 4, "launches": 4}), flush=True)
+        return
+    if args.sweep:
+        sweep(args, dev)
         return
     t0 = time.time()
     wl = synth.cfg2(device=dev, precision="f32", hours=args.hours)
@@ -368,6 +375,51 @@ def main():
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def sweep(args, dev):
+    """Gridding time against full support and image size (the paper's Figs. 7 and 8 vary
+    these two at fixed data): the whole wproj_grid call (binning, tile gridder, reduce),
+    autotuned per point, on the benchmark's visibilities."""
+    import torch
+
+    import paper_1905_03213_amd as W
+    import synth
+
+    wl = synth.cfg2(device=dev, precision="f32", hours=args.hours)
+    cell = wl.params["cell_rad"]
+    w_max = wl.params["w_max"]
+    data = {"f32": (wl.vis.to(torch.complex64), wl.weight.to(torch.float32)),
+            "f64": (wl.vis, wl.weight)}
+    points = [(s_full, 2048) for s_full in range(3, 17)] + [(8, n) for n in (128, 256, 512, 1024, 4096)]
+    for s_full, n in points:
+        m = synth.kernel_image_size_rule(w_max, n * cell, s_full, s_full)
+        params = {**wl.params, "n": n, "support": s_full, "support_per_plane": None,
+                  "kernel_image_size": m, "algorithm": "tiled"}
+        for prec in ("f32", "f64"):
+            vis, wt = data[prec]
+            k = W.make_kernels({**params, "precision": prec})
+            ws = k.workspace(wl.nvis)
+            g = k.new_grid()
+            sw = torch.zeros(1, dtype=torch.float64, device=dev)
+            tile, chunk = W.autotune(k, wl.uvw, vis, wt, workspace=ws)
+            W.grid(k, wl.uvw, vis, wt, g, weight_sum=sw, workspace=ws)
+            torch.cuda.synchronize()
+            n_grid = int(round(sw.item()))
+            k.profile(True)
+            k.profile_read()
+            for _ in range(5):
+                W.grid(k, wl.uvw, vis, wt, g, workspace=ws)
+            torch.cuda.synchronize()
+            ph = k.profile_read()
+            k.profile(False)
+            ms = sum(ph[p][0] / max(ph[p][1], 1) for p in ("bin", "grid", "reduce"))
+            print(json.dumps({"sweep": "support" if n == 2048 else "image_size", "support": s_full,
+                              "n": n, "precision": prec, "ms": ms,
+                              "gridded_mvis_per_s": n_grid / ms / 1e3, "tile": tile, "chunk": chunk,
+                              "gridded": n_grid, "kernel_image_size": m}), flush=True)
+            del ws, g
+            k.free()
 
 
 def cpu_baseline(wl, seconds):

@@ -211,11 +211,23 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
   return hipGetLastError();
 }
 
+template <typename Real, typename Rec, typename Tab, int S>
+hipError_t dispatch_fixed(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
+                          const BinWorkspace &W, const void *model, void *out, hipStream_t s) {
+  if constexpr (S > 8) {
+    return launch_one<Real, Rec, Tab, 0>(k, B, ts, W, model, out, s);
+  } else {
+    if (k->s_max == S) return launch_one<Real, Rec, Tab, S>(k, B, ts, W, model, out, s);
+    return dispatch_fixed<Real, Rec, Tab, S + 1>(k, B, ts, W, model, out, s);
+  }
+}
+
+// a fixed support from 3 to 8 (one footprint row per lane of a group) has its own kernel
 template <typename Real, typename Rec, typename Tab>
 hipError_t dispatch(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
                     const BinWorkspace &W, const void *model, void *out, hipStream_t s) {
-  if (k->uniform_support && k->s_max == 8) return launch_one<Real, Rec, Tab, 8>(k, B, ts, W, model, out, s);
-  if (k->uniform_support && k->s_max == 7) return launch_one<Real, Rec, Tab, 7>(k, B, ts, W, model, out, s);
+  if (k->uniform_support && k->s_max >= 3 && k->s_max <= 8)
+    return dispatch_fixed<Real, Rec, Tab, 3>(k, B, ts, W, model, out, s);
   return launch_one<Real, Rec, Tab, 0>(k, B, ts, W, model, out, s);
 }
 

@@ -89,6 +89,9 @@ template <> struct Cx<double> { using T = double2; };
 // overlap per wave.
 constexpr int kGroup = 8;
 constexpr int kMaxWavesPerBlock = 4;
+// fixed supports with a kernel of their own
+constexpr int kMinFixedSupport = 3;
+constexpr int kMaxFixedSupport = 16;
 
 // A row-carrying record (weight, row) turned into W V from the visibility it names.
 template <typename Rec, typename C2>
@@ -127,10 +130,6 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
   C2 *acc = reinterpret_cast<C2 *>(smem_raw) + (size_t)wid * wave_lds;
   const uint32_t n_items = *n_items_ptr;
   const int area = rows * pitch;
-  // fixed support: lane t holds tap (kv, ku) = (t / S, t % S) at offset kv pitch + ku
-  const int lane_off = S > 0 ? (lane / (S > 0 ? S : 1)) * pitch + lane % (S > 0 ? S : 1) : 0;
-  const bool lane_on = S > 0 ? lane < S * S : true;
-  const uint32_t tap_lane = lane_on ? (uint32_t)lane : 0u;
   const __amdgpu_buffer_rsrc_t tab_rsrc =
       __builtin_amdgcn_make_buffer_rsrc((void *)tab, (short)0, (int)tab_bytes, kBufferWord3);
 
@@ -158,35 +157,57 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
       }
     };
 
-    if constexpr (S > 0 && S * S <= 64) {
-      // Direct-fetch path (fixed support, one tap per lane): table taps are loaded one
-      // group of kGroup records ahead of their use.  (Staging the batch in LDS and
-      // reading each record back as an LDS broadcast measured slower than readlanes.)
+    if constexpr (S > 0) {
+      // Direct-fetch path (fixed support): lane t handles tap t of every record, in
+      // kPasses passes of 64 taps when S^2 > 64.  Table taps are loaded one group of
+      // kGroupS records ahead of their use; the group shrinks as the passes grow, so the
+      // prefetched taps stay within a fixed register budget.  (Staging the batch in LDS
+      // and reading each record back as an LDS broadcast measured slower than readlanes.)
       using Tap = decltype(tab_load(tab, 0u));
-      constexpr int kGroups = 64 / kGroup;
+      constexpr int kPasses = (S * S + 63) / 64;
+      constexpr int kGroupS = kPasses == 1 ? kGroup : kPasses == 2 ? kGroup / 2 : kGroup / 4;
+      constexpr int kGroups = 64 / kGroupS;
+      int p_off[kPasses];
+      bool p_on[kPasses];
+      uint32_t p_tap[kPasses];
+#pragma unroll
+      for (int q = 0; q < kPasses; ++q) {
+        const int t = q * 64 + lane;
+        p_on[q] = t < S * S;
+        p_off[q] = (t / S) * pitch + t % S;
+        p_tap[q] = p_on[q] ? (uint32_t)t : 0u;
+      }
       Rec cur;
       load_batch(0, cur);
       for (uint32_t b = 0; b < n_rec; b += 64) {
         Rec nxt;
         const bool more = b + 64 < n_rec;
         if (more) load_batch(b + 64, nxt);
-        Tap c[2][kGroup];
+        Tap c[2][kGroupS][kPasses];
 #pragma unroll
-        for (int i = 0; i < kGroup; ++i) c[0][i] = tab_fetch(tab_rsrc, tap_lane, bcast(cur.tap, i) & kTapMask, tab);
+        for (int i = 0; i < kGroupS; ++i) {
+          const uint32_t tb = bcast(cur.tap, i) & kTapMask;
+#pragma unroll
+          for (int q = 0; q < kPasses; ++q) c[0][i][q] = tab_fetch(tab_rsrc, p_tap[q], tb, tab);
+        }
 #pragma unroll
         for (int gI = 0; gI < kGroups; ++gI) {
           if (gI + 1 < kGroups) {
 #pragma unroll
-            for (int i = 0; i < kGroup; ++i)
-              c[(gI + 1) & 1][i] =
-                  tab_fetch(tab_rsrc, tap_lane, bcast(cur.tap, (gI + 1) * kGroup + i) & kTapMask, tab);
+            for (int i = 0; i < kGroupS; ++i) {
+              const uint32_t tb = bcast(cur.tap, (gI + 1) * kGroupS + i) & kTapMask;
+#pragma unroll
+              for (int q = 0; q < kPasses; ++q) c[(gI + 1) & 1][i][q] = tab_fetch(tab_rsrc, p_tap[q], tb, tab);
+            }
           }
 #pragma unroll
-          for (int i = 0; i < kGroup; ++i) {
-            const int j = gI * kGroup + i;
+          for (int i = 0; i < kGroupS; ++i) {
+            const int j = gI * kGroupS + i;
             const int base = (int)bcast(cur.lds, j);
             const Real rwr = bcast(cur.wr, j), rwi = bcast(cur.wi, j);
-            if (lane_on) accumulate(acc, base + lane_off, rwr, rwi, c[gI & 1][i]);
+#pragma unroll
+            for (int q = 0; q < kPasses; ++q)
+              if (p_on[q]) accumulate(acc, base + p_off[q], rwr, rwi, c[gI & 1][i][q]);
           }
         }
         if (more) cur = nxt;
@@ -288,13 +309,24 @@ hipError_t launch_reduce(const wproj_kernels *k, const BinShape &B, const TileSh
   return hipGetLastError();
 }
 
+template <typename Real, typename Rec, typename Tab, bool PLANNED, int S>
+hipError_t dispatch_fixed(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
+                          const BinWorkspace &W, void *grid, const void *vis, hipStream_t s) {
+  if constexpr (S > kMaxFixedSupport) {
+    return launch_one<Real, Rec, Tab, 0, PLANNED>(k, B, ts, W, grid, vis, s);
+  } else {
+    if (k->s_max == S) return launch_one<Real, Rec, Tab, S, PLANNED>(k, B, ts, W, grid, vis, s);
+    return dispatch_fixed<Real, Rec, Tab, PLANNED, S + 1>(k, B, ts, W, grid, vis, s);
+  }
+}
+
 template <typename Real, typename Rec, typename Tab, bool PLANNED>
 hipError_t dispatch_support(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
                             const BinWorkspace &W, void *grid, const void *vis, hipStream_t s) {
-  if (k->uniform_support && k->s_max == 8)
-    return launch_one<Real, Rec, Tab, 8, PLANNED>(k, B, ts, W, grid, vis, s);
-  if (k->uniform_support && k->s_max == 7)
-    return launch_one<Real, Rec, Tab, 7, PLANNED>(k, B, ts, W, grid, vis, s);
+  // a fixed support from kMinFixedSupport to kMaxFixedSupport has its own kernel;
+  // per-plane supports take the general path
+  if (k->uniform_support && k->s_max >= kMinFixedSupport && k->s_max <= kMaxFixedSupport)
+    return dispatch_fixed<Real, Rec, Tab, PLANNED, kMinFixedSupport>(k, B, ts, W, grid, vis, s);
   return launch_one<Real, Rec, Tab, 0, PLANNED>(k, B, ts, W, grid, vis, s);
 }
 

@@ -75,3 +75,45 @@ def test_tiled_degrid_geometries(geom):
     assert rel_max(got, ref) <= TOL["f32"]
     assert np.count_nonzero(got) == np.count_nonzero(ref)
     k.free()
+
+
+FIXED = [3, 4, 5, 6, 9, 12, 16]
+
+
+def _fixed_params(s_full, prec):
+    return dict(n=192, cell_rad=6e-5, n_wplanes=5, w_max=300.0, support=s_full, oversample=8,
+                kernel_image_size=max(32, 2 * s_full), n_images=1, precision=prec, algorithm="tiled")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("s_full", FIXED)
+def test_tiled_grid_fixed_supports(s_full, prec):
+    """Every fixed support from 3 to 16 has its own gridder kernel (one tap per lane in
+    ceil(S^2 / 64) passes); 6 is the largest that fits one pass with lanes to spare, 9 the
+    first with two passes, 16 the largest with its own kernel."""
+    params = _fixed_params(s_full, prec)
+    uvw, vis, wt = _inputs(params, 5)
+    G, sw, cnt, host = run_grid(params, uvw, vis, wt)
+    (Gr, swr, cr), _, _ = oracle_grid(params, host)
+    assert cnt.tolist() == cr.tolist()
+    assert np.allclose(sw, swr, rtol=1e-12, atol=0)
+    assert rel_max(G, Gr) <= TOL[prec]
+
+
+@pytest.mark.parametrize("s_full", FIXED)
+def test_tiled_degrid_fixed_supports(s_full):
+    params = _fixed_params(s_full, "f32")
+    uvw, _, _ = _inputs(params, 6)
+    plan = R.Plan(params)
+    tabs = R.kernel_tables(plan)
+    n = plan.n
+    rng = np.random.default_rng(8)
+    M = (rng.standard_normal((1, n, n)) + 1j * rng.standard_normal((1, n, n))).astype(np.complex64)
+    k = W.make_kernels(params)
+    out = torch.full((uvw.shape[0],), 7.0 + 7.0j, dtype=torch.complex64, device="cuda")
+    W.degrid(k, torch.as_tensor(uvw).cuda(), torch.as_tensor(M).cuda(), out)
+    ref = R.degrid(plan, tabs, uvw, M.astype(np.complex128))
+    got = out.to(torch.complex128).cpu().numpy()
+    assert rel_max(got, ref) <= TOL["f32"]
+    assert np.count_nonzero(got) == np.count_nonzero(ref)
+    k.free()
