@@ -59,6 +59,9 @@ def parse():
                     help="also time the step replayed from a captured HIP graph")
     ap.add_argument("--tile", type=int, default=0, help="fix the tile side (skips autotuning)")
     ap.add_argument("--chunk", type=int, default=0, help="fix the work-item length (with --tile)")
+    ap.add_argument("--step-only", action="store_true",
+                    help="time the gridding step only (no degridding, plan, regroup, FP64 or "
+                         "FP16-table extras), e.g. for hardware-counter passes")
     ap.add_argument("--sweep", action="store_true",
                     help="only sweep the binned gridding call over full support 3..16 (2048^2) and "
                          "image size 128..4096 (support 8) at a fixed 1e-5 rad cell, FP32 and FP64, "
@@ -192,83 +195,85 @@ def main():
         "hbm_frac": HBM_BYTES_PER_VIS_GRID * n_valid / t_grid / PEAK_HBM,
     }
 
-    # degridding of the same visibilities from the imaged model (adjoint direction)
-    vout = torch.empty(nvis, dtype=torch.complex64, device=dev)
-    W.image(k, W.IMAGE_TO_GRID, g, img, workspace=ws)
-    W.degrid(k, uvw, g, vout, workspace=ws)
-    torch.cuda.synchronize()
-    k.profile(True)
-    reps = max(2, args.steps // 4)
-    for _ in range(reps):
+    if not args.step_only:
+        # degridding of the same visibilities from the imaged model (adjoint direction)
+        vout = torch.empty(nvis, dtype=torch.complex64, device=dev)
+        W.image(k, W.IMAGE_TO_GRID, g, img, workspace=ws)
         W.degrid(k, uvw, g, vout, workspace=ws)
-    torch.cuda.synchronize()
-    dph = k.profile_read()
-    k.profile(False)
-    degrid_ms = dph["degrid"][0] / max(dph["degrid"][1], 1)
+        torch.cuda.synchronize()
+        k.profile(True)
+        reps = max(2, args.steps // 4)
+        for _ in range(reps):
+            W.degrid(k, uvw, g, vout, workspace=ws)
+        torch.cuda.synchronize()
+        dph = k.profile_read()
+        k.profile(False)
+        degrid_ms = dph["degrid"][0] / max(dph["degrid"][1], 1)
 
-    # a plan: the binning kept, then gridding / degridding of new visibilities on the same
-    # rows (an imaging loop's major cycles)
-    plan = W.Plan(k, uvw, wt32)
-    plan.grid(vis32, g)
-    torch.cuda.synchronize()
-    k.profile(True)
-    k.profile_read()
-    for _ in range(reps):
-        g.zero_()
+        # a plan: the binning kept, then gridding / degridding of new visibilities on the same
+        # rows (an imaging loop's major cycles)
+        plan = W.Plan(k, uvw, wt32)
         plan.grid(vis32, g)
-    for _ in range(reps):
-        plan.degrid(g, vout)
-    torch.cuda.synchronize()
-    pph = k.profile_read()
-    k.profile(False)
-    plan.free()
-    planned_grid_ms = sum(pph[ph][0] / max(pph[ph][1], 1) for ph in ("grid", "reduce"))
-    planned_degrid_ms = pph["degrid"][0] / max(pph["degrid"][1], 1)
+        torch.cuda.synchronize()
+        k.profile(True)
+        k.profile_read()
+        for _ in range(reps):
+            g.zero_()
+            plan.grid(vis32, g)
+        for _ in range(reps):
+            plan.degrid(g, vout)
+        torch.cuda.synchronize()
+        pph = k.profile_read()
+        k.profile(False)
+        plan.free()
+        planned_grid_ms = sum(pph[ph][0] / max(pph[ph][1], 1) for ph in ("grid", "reduce"))
+        planned_degrid_ms = pph["degrid"][0] / max(pph["degrid"][1], 1)
 
-    # rows regrouped by baseline (Eqs. 5 and 6) and the rows of uvw and visibilities
-    # gathered into that order: the paper's GPU-side data preparation, on the same rows
-    src = wl.sources
-    n_t, n_bl, n_ch = int(src["n_time"]), int(src["n_bl"]), int(src["n_chan"])
-    n_ant = int(max(np.max(src["ant1"]), np.max(src["ant2"]))) + 1
-    a1 = torch.as_tensor(np.tile(src["ant1"], n_t).astype(np.int32), device=dev)
-    a2 = torch.as_tensor(np.tile(src["ant2"], n_t).astype(np.int32), device=dev)
-    uvw_rows = uvw.view(n_t * n_bl, n_ch, 3)
-    vis_rows = vis32.view(n_t * n_bl, n_ch)
-    uvw_out = torch.empty_like(uvw_rows)
-    vis_out = torch.empty_like(vis_rows)
-    perm, _, _ = W.regroup_rows(a1, a2, n_ant)
-    torch.cuda.synchronize()
-    reps = 5
-    ev0.record(stream)
-    for _ in range(reps):
+        # rows regrouped by baseline (Eqs. 5 and 6) and the rows of uvw and visibilities
+        # gathered into that order: the paper's GPU-side data preparation, on the same rows
+        src = wl.sources
+        n_t, n_bl, n_ch = int(src["n_time"]), int(src["n_bl"]), int(src["n_chan"])
+        n_ant = int(max(np.max(src["ant1"]), np.max(src["ant2"]))) + 1
+        a1 = torch.as_tensor(np.tile(src["ant1"], n_t).astype(np.int32), device=dev)
+        a2 = torch.as_tensor(np.tile(src["ant2"], n_t).astype(np.int32), device=dev)
+        uvw_rows = uvw.view(n_t * n_bl, n_ch, 3)
+        vis_rows = vis32.view(n_t * n_bl, n_ch)
+        uvw_out = torch.empty_like(uvw_rows)
+        vis_out = torch.empty_like(vis_rows)
         perm, _, _ = W.regroup_rows(a1, a2, n_ant)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    regroup_ms = ev0.elapsed_time(ev1) / reps
-    ev0.record(stream)
-    for _ in range(reps):
-        W.gather_rows(perm, uvw_rows, out=uvw_out)
-        W.gather_rows(perm, vis_rows, out=vis_out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    gather_ms = ev0.elapsed_time(ev1) / reps
-    gather_bytes = 2 * (uvw_rows.numel() * 8 + vis_rows.numel() * 8)
-    del uvw_out, vis_out, perm, a1, a2
+        torch.cuda.synchronize()
+        reps = 5
+        ev0.record(stream)
+        for _ in range(reps):
+            perm, _, _ = W.regroup_rows(a1, a2, n_ant)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        regroup_ms = ev0.elapsed_time(ev1) / reps
+        ev0.record(stream)
+        for _ in range(reps):
+            W.gather_rows(perm, uvw_rows, out=uvw_out)
+            W.gather_rows(perm, vis_rows, out=vis_out)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        gather_ms = ev0.elapsed_time(ev1) / reps
+        gather_bytes = 2 * (uvw_rows.numel() * 8 + vis_rows.numel() * 8)
+        del uvw_out, vis_out, perm, a1, a2
 
-    extra = {"phases_ms": per, "degrid": {"ms": degrid_ms, "mvis_per_s": n_valid / degrid_ms / 1e3},
-             "planned": {"grid_ms": planned_grid_ms, "grid_mvis_per_s": n_valid / planned_grid_ms / 1e3,
-                         "degrid_ms": planned_degrid_ms},
-             "regroup_by_baseline": {"rows": n_t * n_bl, "ms": regroup_ms,
-                                     "gather_uvw_vis_ms": gather_ms,
-                                     "gather_gb_per_s": gather_bytes / gather_ms / 1e6},
-             "tuning": {"tile": tile, "chunk": chunk},
+    extra = {"phases_ms": per, "tuning": {"tile": tile, "chunk": chunk},
              "graph_replay_ms_per_step": graph_ms,
              "counters": {"dropped": counters[0], "w_clamped": counters[1], "bad_weight": counters[2]},
              "nvis_total": nvis, "nvis_gridded": n_valid}
+    if not args.step_only:
+        extra.update({
+            "degrid": {"ms": degrid_ms, "mvis_per_s": n_valid / degrid_ms / 1e3},
+            "planned": {"grid_ms": planned_grid_ms, "grid_mvis_per_s": n_valid / planned_grid_ms / 1e3,
+                        "degrid_ms": planned_degrid_ms},
+            "regroup_by_baseline": {"rows": n_t * n_bl, "ms": regroup_ms, "gather_uvw_vis_ms": gather_ms,
+                                    "gather_gb_per_s": gather_bytes / gather_ms / 1e6}})
     del ws
     k.free()
 
-    if not args.no_fp64:
+    if not args.no_fp64 and not args.step_only:
         p64 = {**wl.params, "precision": "f64", "algorithm": "plain"}
         k64 = W.make_kernels(p64)
         g64 = k64.new_grid()
@@ -318,7 +323,7 @@ def main():
         del g64, ws64
         k64.free()
 
-    if not args.no_fp64:
+    if not args.no_fp64 and not args.step_only:
         # FP32 accumulation with FP16 kernel tables (half the table bytes the gridder fetches)
         kh = W.make_kernels({**params, "precision": "f32_f16table", "tile": 0, "chunk": 0})
         gh = kh.new_grid()
