@@ -92,3 +92,49 @@ def test_graph_replays_match_eager(n_images):
         assert rel_max(got_img[:, q:-q, q:-q].double().cpu().numpy(),
                        img[:, q:-q, q:-q].double().cpu().numpy()) <= 1e-5
     k.free()
+
+
+def test_planned_step_replays_match_eager():
+    """A kept plan's gridding plus imaging, captured once and replayed for new visibilities
+    (the body of an imaging loop)."""
+    wl = synth.small_tracks(n=256, cell=8e-5, n_chan=8, hours=2.0, dt_s=30.0)
+    k = W.make_kernels({**wl.params, "precision": "f32", "algorithm": "tiled"})
+    n = wl.params["n"]
+    uvw = wl.uvw.cuda()
+    vis = wl.vis.to(torch.complex64).cuda()
+    wt = wl.weight.float().cuda()
+    sw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    plan = W.Plan(k, uvw, wt, weight_sum=sw)
+    ws = k.workspace(0)
+    g = k.new_grid()
+    img = torch.empty((1, n, n), dtype=torch.float32, device="cuda")
+
+    def step():
+        g.zero_()
+        plan.grid(vis, g)
+        W.image(k, W.GRID_TO_IMAGE, g, img, sw, workspace=ws)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2)
+    q = n // 4
+    for rep in range(3):
+        vis.mul_(float(rng.uniform(0.5, 2.0)))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = img.clone()
+        step()
+        torch.cuda.synchronize()
+        assert rel_max(got[:, q:-q, q:-q].double().cpu().numpy(),
+                       img[:, q:-q, q:-q].double().cpu().numpy()) <= 1e-5
+    plan.free()
+    k.free()
