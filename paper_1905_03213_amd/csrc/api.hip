@@ -402,13 +402,16 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
 
   if (hipMalloc(&k->d_supp, sizeof(int32_t) * n_w) != hipSuccess ||
       hipMalloc(&k->d_tab_off, sizeof(int64_t) * (n_w + 1)) != hipSuccess ||
-      hipMalloc(&k->d_tab, (size_t)k->n_taps * k->tap_bytes) != hipSuccess ||
+      hipMalloc(&k->d_tab, (size_t)(k->n_taps + 1) * k->tap_bytes) != hipSuccess ||
       hipMalloc(&k->d_kappa, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&k->d_taper, sizeof(double) * m) != hipSuccess)
     return fail(WPROJ_ENOMEM, "device allocation of kernel tables (%lld taps) failed",
                 (long long)k->n_taps);
   G.supp = k->d_supp;
   G.tab_off = k->d_tab_off;
+  // one zero tap after the last sub-kernel: the gridder's paired fetch reads taps two at a
+  // time and may read it (and then discards it)
+  HIP_TRY(hipMemsetAsync((char *)k->d_tab + (size_t)k->n_taps * k->tap_bytes, 0, k->tap_bytes, s));
   HIP_TRY(hipMemcpyAsync(k->d_supp, supp.data(), sizeof(int32_t) * n_w, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(k->d_tab_off, k->tab_off_host.data(), sizeof(int64_t) * (n_w + 1),
                          hipMemcpyHostToDevice, s));

@@ -17,13 +17,15 @@
 //
 // Launch is persistent: enough wavefronts to fill every CU pull work items from a queue
 // head in HBM until the queue is empty, which evens out the very uneven per-tile
-// visibility counts of Earth-rotation tracks.  With a fixed support of at most 64 taps,
-// lane t handles tap t of every record: records are loaded 64 at a time and broadcast
-// with readlane, and each record's taps come from one buffer load whose wave-uniform
-// part (the sub-kernel) is a scalar offset.  On this chip the step is bound by those
-// table fetches (64 x 8 bytes per record returned to registers, mostly from L1): with
-// FP16 tables (4 bytes per tap) the same launch runs about a third faster.
+// visibility counts of Earth-rotation tracks.  With a fixed support, records are loaded
+// 64 at a time and broadcast with readlane, and each lane handles one tap of every record
+// per pass of 64 taps.  The table fetches (64 x 8 bytes per record returned to registers,
+// mostly from L1) bound a one-record-per-load loop on this chip, so with FP32 arithmetic
+// two records share a load: two adjacent taps per lane, one record per half wavefront,
+// then a half-wavefront swap.  What is left is mostly vector-ALU issue (the four FMAs,
+// the broadcasts and the addressing per record and tap lane).
 #include <algorithm>
+#include <type_traits>
 
 #include "wproj_tiled.h"
 
@@ -63,6 +65,46 @@ __device__ inline float2 tab_fetch(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint
 }
 // gfx9 buffer descriptor word 3: 32-bit data format, no swizzle
 constexpr int kBufferWord3 = 0x00020000;
+
+// Paired tap fetch (FP32 arithmetic): one load brings two adjacent taps per lane, lanes
+// 0-31 for the first record of a pair and lanes 32-63 for the second, so a pair of
+// records costs one wide load instead of two narrow ones.  A swap of the upper half of
+// the first taps with the lower half of the second taps (v_permlane32_swap, a VALU
+// operation) then leaves lane L with tap 2 (L mod 32) + L / 32 of each record.
+template <typename Tab> struct TapPair;
+template <> struct TapPair<float2> {
+  typedef uint32_t Raw __attribute__((ext_vector_type(4)));
+  static constexpr uint32_t kTapBytes = 8;
+  __device__ static Raw load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
+  }
+  __device__ static void split(const Raw &v, float2 &first, float2 &second) {
+    const uint32_t a_re = v[0], a_im = v[1], b_re = v[2], b_im = v[3];
+    const auto re = __builtin_amdgcn_permlane32_swap(a_re, b_re, false, false);
+    const auto im = __builtin_amdgcn_permlane32_swap(a_im, b_im, false, false);
+    const uint32_t f_re = re[0], s_re = re[1], f_im = im[0], s_im = im[1];
+    first = make_float2(__uint_as_float(f_re), __uint_as_float(f_im));
+    second = make_float2(__uint_as_float(s_re), __uint_as_float(s_im));
+  }
+};
+template <> struct TapPair<half2c> {
+  typedef uint32_t Raw __attribute__((ext_vector_type(2)));
+  static constexpr uint32_t kTapBytes = 4;
+  __device__ static Raw load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    return __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+  }
+  __device__ static void split(const Raw &v, float2 &first, float2 &second) {
+    const uint32_t a = v[0], b = v[1];
+    const auto x = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    const uint32_t f = x[0], s = x[1];
+    half2c hf, hs;
+    __builtin_memcpy(&hf, &f, 4);
+    __builtin_memcpy(&hs, &s, 4);
+    first = make_float2((float)hf.re, (float)hf.im);
+    second = make_float2((float)hs.re, (float)hs.im);
+  }
+};
+template <typename Tab> constexpr bool kPairedTab = std::is_same_v<Tab, float2> || std::is_same_v<Tab, half2c>;
 
 __device__ inline float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -157,7 +199,81 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
       }
     };
 
-    if constexpr (S > 0) {
+    if constexpr (S > 0 && kPairedTab<Tab>) {
+      // Paired direct-fetch path (fixed support, FP32 arithmetic): as below, but the taps
+      // of records 2i and 2i+1 arrive with one load, and lane L handles footprint tap
+      // t = 64 q + 2 (L mod 32) + L / 32 in pass q.  The table holds one padding tap
+      // after its last sub-kernel, so the second tap of a pair never leaves it.
+      using P = TapPair<Tab>;
+      using Raw = typename P::Raw;
+      constexpr int kPasses = (S * S + 63) / 64;
+      constexpr int kGroupS = kPasses == 1 ? kGroup : kPasses == 2 ? kGroup / 2 : kGroup / 4;
+      constexpr int kPairs = kGroupS / 2;
+      constexpr int kGroups = 64 / kGroupS;
+      const int half = lane >> 5;
+      const int j2 = 2 * (lane & 31);
+      // all ones in the upper half of the wavefront; opaque to the compiler, which would
+      // otherwise turn the AND below back into a per-pair vector select
+      uint32_t upper = half ? 0xffffffffu : 0u;
+      asm volatile("" : "+v"(upper));
+      int p_off[kPasses];
+      bool p_on[kPasses];
+      uint32_t p_pair[kPasses];  // byte offset of the lane's tap pair inside a sub-kernel
+#pragma unroll
+      for (int q = 0; q < kPasses; ++q) {
+        const int t = q * 64 + j2 + half;
+        p_on[q] = t < S * S;
+        p_off[q] = (t / S) * pitch + t % S;
+        p_pair[q] = (q * 64 + j2 < S * S ? (uint32_t)(q * 64 + j2) : 0u) * P::kTapBytes;
+      }
+      // Byte offset of the lane's tap pair: first record's sub-kernel plus, in the upper
+      // half, the (modulo 2^32) distance to the second record's; the scalar unit forms
+      // both, so the select costs one vector AND.
+      auto fetch = [&](const Rec &batch, int j, int q) {
+        const uint32_t a = (bcast(batch.tap, j) & kTapMask) * P::kTapBytes;
+        const uint32_t d = (bcast(batch.tap, j + 1) & kTapMask) * P::kTapBytes - a;
+        return P::load(tab_rsrc, a + (upper & d) + p_pair[q]);
+      };
+      Rec cur;
+      load_batch(0, cur);
+      for (uint32_t b = 0; b < n_rec; b += 64) {
+        Rec nxt;
+        const bool more = b + 64 < n_rec;
+        if (more) load_batch(b + 64, nxt);
+        Raw c[2][kPairs][kPasses];
+#pragma unroll
+        for (int i = 0; i < kPairs; ++i)
+#pragma unroll
+          for (int q = 0; q < kPasses; ++q) c[0][i][q] = fetch(cur, 2 * i, q);
+#pragma unroll
+        for (int gI = 0; gI < kGroups; ++gI) {
+          if (gI + 1 < kGroups) {
+#pragma unroll
+            for (int i = 0; i < kPairs; ++i)
+#pragma unroll
+              for (int q = 0; q < kPasses; ++q)
+                c[(gI + 1) & 1][i][q] = fetch(cur, (gI + 1) * kGroupS + 2 * i, q);
+          }
+#pragma unroll
+          for (int i = 0; i < kPairs; ++i) {
+            const int j = gI * kGroupS + 2 * i;
+            const int base0 = (int)bcast(cur.lds, j), base1 = (int)bcast(cur.lds, j + 1);
+            const Real wr0 = bcast(cur.wr, j), wi0 = bcast(cur.wi, j);
+            const Real wr1 = bcast(cur.wr, j + 1), wi1 = bcast(cur.wi, j + 1);
+#pragma unroll
+            for (int q = 0; q < kPasses; ++q) {
+              float2 t0, t1;
+              P::split(c[gI & 1][i][q], t0, t1);
+              if (p_on[q]) {
+                accumulate(acc, base0 + p_off[q], wr0, wi0, t0);
+                accumulate(acc, base1 + p_off[q], wr1, wi1, t1);
+              }
+            }
+          }
+        }
+        if (more) cur = nxt;
+      }
+    } else if constexpr (S > 0) {
       // Direct-fetch path (fixed support): lane t handles tap t of every record, in
       // kPasses passes of 64 taps when S^2 > 64.  Table taps are loaded one group of
       // kGroupS records ahead of their use; the group shrinks as the passes grow, so the
@@ -293,7 +409,7 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
   const unsigned blocks = (unsigned)(k->n_cu * per_cu);
   const int wave_lds = (int)(ts.lds_bytes / (2 * sizeof(Real)));
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, s, k->geo, B, ts.pitch,
-                     ts.rows, wave_lds, (const Tab *)k->d_tab, (uint32_t)(k->n_taps * sizeof(Tab)),
+                     ts.rows, wave_lds, (const Tab *)k->d_tab, (uint32_t)((k->n_taps + 1) * sizeof(Tab)),
                      (const Rec *)W.rec, W.items, W.choff + B.n_tiles, W.counter,
                      (typename Cx<Real>::T *)W.partial, (const typename Cx<Real>::T *)vis);
   return hipGetLastError();

@@ -15,7 +15,7 @@ from gpu_util import oracle_grid, rel_max, run_grid
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-5}
+TOL = {"f64": 1e-12, "f32": 1e-5, "f32_f16table": 1e-3}
 
 GEOMETRIES = {
     "one_plane": dict(n=256, cell_rad=5e-5, n_wplanes=1, w_max=0.0, support=8, oversample=8,
@@ -85,12 +85,15 @@ def _fixed_params(s_full, prec):
                 kernel_image_size=max(32, 2 * s_full), n_images=1, precision=prec, algorithm="tiled")
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_f16table"])
 @pytest.mark.parametrize("s_full", FIXED)
 def test_tiled_grid_fixed_supports(s_full, prec):
     """Every fixed support from 3 to 16 has its own gridder kernel (one tap per lane in
     ceil(S^2 / 64) passes); 6 is the largest that fits one pass with lanes to spare, 9 the
-    first with two passes, 16 the largest with its own kernel."""
+    first with two passes, 16 the largest with its own kernel.  With FP32 arithmetic the
+    taps of two records arrive in one load, two adjacent taps per lane; an odd S^2 makes
+    the last pair of a sub-kernel reach one tap beyond it (into the next sub-kernel, or the
+    padding tap after the table)."""
     params = _fixed_params(s_full, prec)
     uvw, vis, wt = _inputs(params, 5)
     G, sw, cnt, host = run_grid(params, uvw, vis, wt)
