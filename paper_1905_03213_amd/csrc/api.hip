@@ -211,6 +211,11 @@ BinShape bin_shape(const wproj_kernels *k) {
   B.nty = B.ntx;
   B.kw = k->plane_in_key ? k->params.n_wplanes : 1;
   B.chunk = k->chunk;
+  // a fixed support with a kernel of its own, and sub-kernel numbers that fit above the
+  // LDS offset
+  const int64_t n_sub = (int64_t)k->params.n_wplanes * k->params.oversample * k->params.oversample;
+  B.pack_sub = k->uniform_support && k->s_max >= kMinFixedSupport && k->s_max <= kMaxFixedSupport &&
+               n_sub <= (1ll << (32 - kLdsBits));
   B.n_tiles = (int64_t)k->params.n_images * B.ntx * B.nty;
   B.n_keys = B.n_tiles * B.kw;
   return B;

@@ -152,6 +152,7 @@ __global__ void __launch_bounds__(256)
   Rec r;
   const int lx = f.x0 & (B.tile - 1), ly = f.y0 & (B.tile - 1);
   r.lds = (uint32_t)(ly * B.pitch + lx);
+  if (B.pack_sub) r.lds |= (uint32_t)((f.p * G.O + f.ov) * G.O + f.ou) << kLdsBits;
   r.tap = (uint32_t)(G.tab_off[f.p] + (uint32_t)((f.ov * G.O + f.ou) * S * S)) |
           ((uint32_t)(S - 1) << kTapBits);
   if (vis) {

@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
       auto fetch = [&](const Rec &c, int t, C2 *tap_row, uint32_t &tb_out, int &base_out, uint32_t &row_out) {
         const int j = t * 8 + grp;
         const uint32_t tp = (uint32_t)__shfl((int)c.tap, j, 64);
-        base_out = __shfl((int)c.lds, j, 64);
+        base_out = __shfl((int)c.lds, j, 64) & (int)kLdsMask;
         row_out = (uint32_t)__shfl((int)get_row(c), j, 64);
         tb_out = tp & kTapMask;
         const uint32_t kv = r < S ? (uint32_t)r : 0u;
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
         const Rec rr = rec[valid ? jr : w.begin];
         const int Sr = S > 0 ? S : (int)(rr.tap >> kTapBits) + 1;
         const uint32_t tb = rr.tap & kTapMask;
-        const int base = (int)rr.lds;
+        const int base = (int)(rr.lds & kLdsMask);
         Real re = 0, im = 0;
         if (valid) {
           for (int kv = r; kv < Sr; kv += 8) {

@@ -131,9 +131,6 @@ template <> struct Cx<double> { using T = double2; };
 // overlap per wave.
 constexpr int kGroup = 8;
 constexpr int kMaxWavesPerBlock = 4;
-// fixed supports with a kernel of their own
-constexpr int kMinFixedSupport = 3;
-constexpr int kMaxFixedSupport = 16;
 
 // A row-carrying record (weight, row) turned into W V from the visibility it names.
 template <typename Rec, typename C2>
@@ -225,13 +222,18 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         p_on[q] = t < S * S;
         p_off[q] = (t / S) * pitch + t % S;
         p_pair[q] = (q * 64 + j2 < S * S ? (uint32_t)(q * 64 + j2) : 0u) * P::kTapBytes;
+        // hides the value's range, so that the offset below stays one three-way add
+        asm volatile("" : "+v"(p_pair[q]));
       }
       // Byte offset of the lane's tap pair: first record's sub-kernel plus, in the upper
       // half, the (modulo 2^32) distance to the second record's; the scalar unit forms
       // both, so the select costs one vector AND.
+      // The records carry their sub-kernel number above the LDS offset (one broadcast
+      // for both); the sub-kernel's first tap is that number times S^2.
+      constexpr uint32_t kSubBytes = S * S * P::kTapBytes;
       auto fetch = [&](const Rec &batch, int j, int q) {
-        const uint32_t a = (bcast(batch.tap, j) & kTapMask) * P::kTapBytes;
-        const uint32_t d = (bcast(batch.tap, j + 1) & kTapMask) * P::kTapBytes - a;
+        const uint32_t a = (bcast(batch.lds, j) >> kLdsBits) * kSubBytes;
+        const uint32_t d = (bcast(batch.lds, j + 1) >> kLdsBits) * kSubBytes - a;
         return P::load(tab_rsrc, a + (upper & d) + p_pair[q]);
       };
       Rec cur;
@@ -257,7 +259,8 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
 #pragma unroll
           for (int i = 0; i < kPairs; ++i) {
             const int j = gI * kGroupS + 2 * i;
-            const int base0 = (int)bcast(cur.lds, j), base1 = (int)bcast(cur.lds, j + 1);
+            const int base0 = (int)(bcast(cur.lds, j) & kLdsMask);
+            const int base1 = (int)(bcast(cur.lds, j + 1) & kLdsMask);
             const Real wr0 = bcast(cur.wr, j), wi0 = bcast(cur.wi, j);
             const Real wr1 = bcast(cur.wr, j + 1), wi1 = bcast(cur.wi, j + 1);
 #pragma unroll
@@ -302,7 +305,7 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         Tap c[2][kGroupS][kPasses];
 #pragma unroll
         for (int i = 0; i < kGroupS; ++i) {
-          const uint32_t tb = bcast(cur.tap, i) & kTapMask;
+          const uint32_t tb = (bcast(cur.lds, i) >> kLdsBits) * (uint32_t)(S * S);
 #pragma unroll
           for (int q = 0; q < kPasses; ++q) c[0][i][q] = tab_fetch(tab_rsrc, p_tap[q], tb, tab);
         }
@@ -311,7 +314,7 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
           if (gI + 1 < kGroups) {
 #pragma unroll
             for (int i = 0; i < kGroupS; ++i) {
-              const uint32_t tb = bcast(cur.tap, (gI + 1) * kGroupS + i) & kTapMask;
+              const uint32_t tb = (bcast(cur.lds, (gI + 1) * kGroupS + i) >> kLdsBits) * (uint32_t)(S * S);
 #pragma unroll
               for (int q = 0; q < kPasses; ++q) c[(gI + 1) & 1][i][q] = tab_fetch(tab_rsrc, p_tap[q], tb, tab);
             }
@@ -319,7 +322,7 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
 #pragma unroll
           for (int i = 0; i < kGroupS; ++i) {
             const int j = gI * kGroupS + i;
-            const int base = (int)bcast(cur.lds, j);
+            const int base = (int)(bcast(cur.lds, j) & kLdsMask);
             const Real rwr = bcast(cur.wr, j), rwi = bcast(cur.wi, j);
 #pragma unroll
             for (int q = 0; q < kPasses; ++q)
@@ -337,7 +340,7 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         const uint32_t tp = rr.tap;
         const int Sr = S > 0 ? S : (int)(tp >> kTapBits) + 1;
         const uint32_t tb = tp & kTapMask;
-        const int base = (int)rr.lds;
+        const int base = (int)(rr.lds & kLdsMask);
         for (int t = lane; t < Sr * Sr; t += 64) {
           const int kv = t / Sr, ku = t - kv * Sr;
           accumulate(acc, base + kv * pitch + ku, rr.wr, rr.wi, tab_load(tab, tb + t));
@@ -439,9 +442,10 @@ hipError_t dispatch_fixed(const wproj_kernels *k, const BinShape &B, const TileS
 template <typename Real, typename Rec, typename Tab, bool PLANNED>
 hipError_t dispatch_support(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
                             const BinWorkspace &W, void *grid, const void *vis, hipStream_t s) {
-  // a fixed support from kMinFixedSupport to kMaxFixedSupport has its own kernel;
+  // a fixed support from kMinFixedSupport to kMaxFixedSupport has its own kernel, which
+  // takes the sub-kernel from the packed LDS field (pack_sub is set exactly then);
   // per-plane supports take the general path
-  if (k->uniform_support && k->s_max >= kMinFixedSupport && k->s_max <= kMaxFixedSupport)
+  if (B.pack_sub)
     return dispatch_fixed<Real, Rec, Tab, PLANNED, kMinFixedSupport>(k, B, ts, W, grid, vis, s);
   return launch_one<Real, Rec, Tab, 0, PLANNED>(k, B, ts, W, grid, vis, s);
 }

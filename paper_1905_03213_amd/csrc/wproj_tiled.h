@@ -10,12 +10,22 @@ namespace wproj {
 constexpr int kTapBits = 26;
 constexpr uint32_t kTapMask = (1u << kTapBits) - 1u;
 
+// Bits of Record::lds holding the LDS offset; a tile copy has at most (64 + 31) x 104 =
+// 9880 cells.  When BinShape::pack_sub is set, the bits above hold the sub-kernel number
+// p O^2 + ov O + ou, so that with a uniform support S the first tap is that number times
+// S^2 and the fixed-support gridders read one field instead of two.
+constexpr int kLdsBits = 14;
+constexpr uint32_t kLdsMask = (1u << kLdsBits) - 1u;
+// Fixed supports with gridder kernels of their own.
+constexpr int kMinFixedSupport = 3;
+constexpr int kMaxFixedSupport = 16;
+
 // Partial accumulators per image (weight sums) and per counter, spread by block index.
 constexpr int kSlots = 256;
 
 // One binned visibility: the LDS offset of its first cell inside its tile's private
-// copy ((y0 - tile y0) pitch + (x0 - tile x0)), its sub-kernel (first tap | (S-1) << 26)
-// and W V at the path's precision.
+// copy ((y0 - tile y0) pitch + (x0 - tile x0), optionally with the sub-kernel number
+// above it), its sub-kernel (first tap | (S-1) << 26) and W V at the path's precision.
 struct RecordF32 {
   uint32_t lds;
   uint32_t tap;
@@ -58,6 +68,7 @@ struct BinShape {
   int ntx, nty;
   int kw;
   int chunk;         // max records per work item
+  int pack_sub;      // records carry the sub-kernel number in Record::lds (fixed support)
   int64_t n_tiles;   // n_images * ntx * nty
   int64_t n_keys;    // n_tiles * kw
 };
