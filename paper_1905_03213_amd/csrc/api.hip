@@ -164,6 +164,7 @@ void destroy(wproj_kernels *k) {
   (void)hipFree(k->d_supp);
   (void)hipFree(k->d_tab_off);
   (void)hipFree(k->d_tab);
+  (void)hipFree(k->d_tab_pair);
   (void)hipFree(k->d_kappa);
   (void)hipFree(k->d_taper);
   delete k;
@@ -407,16 +408,13 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
 
   if (hipMalloc(&k->d_supp, sizeof(int32_t) * n_w) != hipSuccess ||
       hipMalloc(&k->d_tab_off, sizeof(int64_t) * (n_w + 1)) != hipSuccess ||
-      hipMalloc(&k->d_tab, (size_t)(k->n_taps + 1) * k->tap_bytes) != hipSuccess ||
+      hipMalloc(&k->d_tab, (size_t)k->n_taps * k->tap_bytes) != hipSuccess ||
       hipMalloc(&k->d_kappa, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&k->d_taper, sizeof(double) * m) != hipSuccess)
     return fail(WPROJ_ENOMEM, "device allocation of kernel tables (%lld taps) failed",
                 (long long)k->n_taps);
   G.supp = k->d_supp;
   G.tab_off = k->d_tab_off;
-  // one zero tap after the last sub-kernel: the gridder's paired fetch reads taps two at a
-  // time and may read it (and then discards it)
-  HIP_TRY(hipMemsetAsync((char *)k->d_tab + (size_t)k->n_taps * k->tap_bytes, 0, k->tap_bytes, s));
   HIP_TRY(hipMemcpyAsync(k->d_supp, supp.data(), sizeof(int32_t) * n_w, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(k->d_tab_off, k->tab_off_host.data(), sizeof(int64_t) * (n_w + 1),
                          hipMemcpyHostToDevice, s));
@@ -443,6 +441,16 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
                              (double2 *)tmp.p[2], (double2 *)tmp.p[3], s));
     HIP_TRY(launch_normalise((const double2 *)tmp.p[3], so_max, O, k->d_supp, k->d_tab_off, p0, np,
                              params->precision, k->d_tab, s));
+  }
+
+  // pair-ordered copy for the fixed-support FP32 gridder
+  if (params->precision != WPROJ_F64 && k->uniform_support && k->s_max >= kMinFixedSupport &&
+      k->s_max <= kMaxFixedSupport) {
+    k->pair_stride = pair_table_stride(k->s_max);
+    const int64_t n_sub = (int64_t)n_w * O * O;
+    if (hipMalloc(&k->d_tab_pair, (size_t)(n_sub * k->pair_stride) * k->tap_bytes) != hipSuccess)
+      return fail(WPROJ_ENOMEM, "device allocation of the pair-ordered table failed");
+    HIP_TRY(launch_pair_table(k, s));
   }
 
   // FFT plans (batched over images, in place, unnormalised)

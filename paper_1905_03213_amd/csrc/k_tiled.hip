@@ -66,11 +66,11 @@ __device__ inline float2 tab_fetch(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint
 // gfx9 buffer descriptor word 3: 32-bit data format, no swizzle
 constexpr int kBufferWord3 = 0x00020000;
 
-// Paired tap fetch (FP32 arithmetic): one load brings two adjacent taps per lane, lanes
+// Paired tap fetch (FP32 arithmetic): one load brings two table entries per lane, lanes
 // 0-31 for the first record of a pair and lanes 32-63 for the second, so a pair of
 // records costs one wide load instead of two narrow ones.  A swap of the upper half of
-// the first taps with the lower half of the second taps (v_permlane32_swap, a VALU
-// operation) then leaves lane L with tap 2 (L mod 32) + L / 32 of each record.
+// the first entries with the lower half of the second entries (v_permlane32_swap, a
+// VALU operation) then leaves every lane with the same tap of both records.
 template <typename Tab> struct TapPair;
 template <> struct TapPair<float2> {
   typedef uint32_t Raw __attribute__((ext_vector_type(4)));
@@ -198,39 +198,48 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
 
     if constexpr (S > 0 && kPairedTab<Tab>) {
       // Paired direct-fetch path (fixed support, FP32 arithmetic): as below, but the taps
-      // of records 2i and 2i+1 arrive with one load, and lane L handles footprint tap
-      // t = 64 q + 2 (L mod 32) + L / 32 in pass q.  The table holds one padding tap
-      // after its last sub-kernel, so the second tap of a pair never leaves it.
+      // of records 2i and 2i+1 arrive with one load.
       using P = TapPair<Tab>;
       using Raw = typename P::Raw;
       constexpr int kPasses = (S * S + 63) / 64;
       constexpr int kGroupS = kPasses == 1 ? kGroup : kPasses == 2 ? kGroup / 2 : kGroup / 4;
       constexpr int kPairs = kGroupS / 2;
       constexpr int kGroups = 64 / kGroupS;
+      // The table is the pair-ordered copy: in pass q (n_q taps, h_q = ceil(n_q / 2)),
+      // entries 2j and 2j+1 hold taps 64q + j and 64q + h_q + j.  Lanes j and 32 + j load
+      // entry pair j of records 2i and 2i+1; after the swap, lane j (< 32) holds tap
+      // 64q + j and lane 32 + j tap 64q + h_q + j of both records.  In full passes that
+      // is tap 64q + lane, whose 64-bit LDS accesses the row pitch keeps free of bank
+      // conflicts (pairs of adjacent taps would put each half wavefront on every second
+      // column of eight rows, which no uniform pitch spreads over all banks).
       const int half = lane >> 5;
-      const int j2 = 2 * (lane & 31);
+      const int j = lane & 31;
       // all ones in the upper half of the wavefront; opaque to the compiler, which would
       // otherwise turn the AND below back into a per-pair vector select
       uint32_t upper = half ? 0xffffffffu : 0u;
       asm volatile("" : "+v"(upper));
       int p_off[kPasses];
       bool p_on[kPasses];
-      uint32_t p_pair[kPasses];  // byte offset of the lane's tap pair inside a sub-kernel
+      uint32_t p_pair[kPasses];  // byte offset of the lane's entry pair inside a sub-kernel
 #pragma unroll
       for (int q = 0; q < kPasses; ++q) {
-        const int t = q * 64 + j2 + half;
-        p_on[q] = t < S * S;
-        p_off[q] = (t / S) * pitch + t % S;
-        p_pair[q] = (q * 64 + j2 < S * S ? (uint32_t)(q * 64 + j2) : 0u) * P::kTapBytes;
+        const int n_q = S * S - 64 * q < 64 ? S * S - 64 * q : 64;
+        const int h_q = (n_q + 1) / 2;
+        const int t = 64 * q + (half ? h_q : 0) + j;
+        p_on[q] = half ? j < n_q - h_q : j < h_q;
+        p_off[q] = p_on[q] ? (t / S) * pitch + t % S : 0;
+        p_pair[q] = (j < h_q ? (uint32_t)(64 * q + 2 * j) : 0u) * P::kTapBytes;
         // hides the value's range, so that the offset below stays one three-way add
         asm volatile("" : "+v"(p_pair[q]));
       }
-      // Byte offset of the lane's tap pair: first record's sub-kernel plus, in the upper
+      // Byte offset of the lane's entry pair: first record's sub-kernel plus, in the upper
       // half, the (modulo 2^32) distance to the second record's; the scalar unit forms
       // both, so the select costs one vector AND.
       // The records carry their sub-kernel number above the LDS offset (one broadcast
-      // for both); the sub-kernel's first tap is that number times S^2.
-      constexpr uint32_t kSubBytes = S * S * P::kTapBytes;
+      // for both); a sub-kernel takes kStride entries of the pair-ordered table.
+      constexpr int kLast = S * S - 64 * (kPasses - 1);
+      constexpr uint32_t kStride = 64 * (kPasses - 1) + 2 * ((kLast + 1) / 2);
+      constexpr uint32_t kSubBytes = kStride * P::kTapBytes;
       auto fetch = [&](const Rec &batch, int j, int q) {
         const uint32_t a = (bcast(batch.lds, j) >> kLdsBits) * kSubBytes;
         const uint32_t d = (bcast(batch.lds, j + 1) >> kLdsBits) * kSubBytes - a;
@@ -411,8 +420,14 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   const unsigned blocks = (unsigned)(k->n_cu * per_cu);
   const int wave_lds = (int)(ts.lds_bytes / (2 * sizeof(Real)));
+  // the paired fixed-support kernels read the pair-ordered table
+  const bool paired = S > 0 && kPairedTab<Tab>;
+  if (paired && (!k->d_tab_pair || k->pair_stride != pair_table_stride(S))) return hipErrorInvalidValue;
+  const int64_t n_sub = (int64_t)k->params.n_wplanes * k->params.oversample * k->params.oversample;
+  const Tab *tab = (const Tab *)(paired ? k->d_tab_pair : k->d_tab);
+  const int64_t tab_entries = paired ? n_sub * k->pair_stride : k->n_taps;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, s, k->geo, B, ts.pitch,
-                     ts.rows, wave_lds, (const Tab *)k->d_tab, (uint32_t)((k->n_taps + 1) * sizeof(Tab)),
+                     ts.rows, wave_lds, tab, (uint32_t)(tab_entries * sizeof(Tab)),
                      (const Rec *)W.rec, W.items, W.choff + B.n_tiles, W.counter,
                      (typename Cx<Real>::T *)W.partial, (const typename Cx<Real>::T *)vis);
   return hipGetLastError();
@@ -457,7 +472,48 @@ hipError_t dispatch_planned(const wproj_kernels *k, const BinShape &B, const Til
              : dispatch_support<Real, Rec, Tab, false>(k, B, ts, W, grid, vis, s);
 }
 
+// Fills the pair-ordered table: one thread per entry.  In pass q of a sub-kernel (n_q
+// taps, h = ceil(n_q / 2)), entry 2j is tap 64q + j and entry 2j+1 tap 64q + h + j, or
+// zero where n_q is odd and that tap does not exist.
+template <typename Tab>
+__global__ void __launch_bounds__(256)
+    pair_table_kernel(const Tab *__restrict__ src, int64_t n_sub, int s2, int stride, Tab *__restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_sub * stride) return;
+  const int64_t sub = i / stride;
+  const int e = (int)(i - sub * stride);
+  const int q = e / 64, r = e - 64 * q;
+  const int n_q = s2 - 64 * q < 64 ? s2 - 64 * q : 64;
+  const int h = (n_q + 1) / 2;
+  const int jj = r >> 1;
+  const bool second = r & 1;
+  const int t = 64 * q + (second ? h : 0) + jj;
+  Tab v{};
+  if (second ? jj < n_q - h : jj < h) v = src[sub * s2 + t];
+  dst[i] = v;
+}
+
 }  // namespace
+
+int64_t pair_table_stride(int S) {
+  const int passes = (S * S + 63) / 64;
+  const int last = S * S - 64 * (passes - 1);
+  return 64 * (passes - 1) + 2 * ((last + 1) / 2);
+}
+
+hipError_t launch_pair_table(const wproj_kernels *k, hipStream_t s) {
+  const int S = k->s_max;
+  const int64_t n_sub = (int64_t)k->params.n_wplanes * k->params.oversample * k->params.oversample;
+  const int64_t total = n_sub * k->pair_stride;
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  if (k->params.precision == WPROJ_F32)
+    hipLaunchKernelGGL(pair_table_kernel<float2>, dim3(blocks), dim3(256), 0, s, (const float2 *)k->d_tab,
+                       n_sub, S * S, (int)k->pair_stride, (float2 *)k->d_tab_pair);
+  else
+    hipLaunchKernelGGL(pair_table_kernel<half2c>, dim3(blocks), dim3(256), 0, s, (const half2c *)k->d_tab,
+                       n_sub, S * S, (int)k->pair_stride, (half2c *)k->d_tab_pair);
+  return hipGetLastError();
+}
 
 TileShape tile_shape(const wproj_kernels *k, int tile) {
   // One wavefront's private tile: rows = T + S_max - 1 complex cells per side.  The row

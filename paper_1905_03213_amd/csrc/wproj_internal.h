@@ -124,6 +124,11 @@ struct wproj_kernels {
   int64_t *d_tab_off = nullptr;
   void *d_tab = nullptr;  // double2 / float2 / half2c per tap
   int64_t n_taps = 0;
+  // With FP32 arithmetic and a fixed support that has its own gridder kernel: the table
+  // again, each pass of 64 taps of a sub-kernel stored as pairs (t, t + h), h = half the
+  // pass rounded up, for the gridder's two-records-per-load fetch.
+  void *d_tab_pair = nullptr;
+  int64_t pair_stride = 0;  // entries per sub-kernel (S^2 rounded up to even)
   size_t tap_bytes = 0;
   double *d_kappa = nullptr;
   double *d_taper = nullptr;

@@ -114,6 +114,10 @@ struct TileShape {
   size_t lds_bytes;
 };
 TileShape tile_shape(const wproj_kernels *k, int tile);
+// Entries per sub-kernel of the pair-ordered table for support S, and the launch that
+// fills k->d_tab_pair from k->d_tab.
+int64_t pair_table_stride(int S);
+hipError_t launch_pair_table(const wproj_kernels *k, hipStream_t s);
 // The tile gridder into the work items' partial tiles, then their sum into the grid.
 // With vis != nullptr the records are row-carrying (a plan) and W V is formed from vis.
 hipError_t launch_tiled_grid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
