@@ -91,9 +91,8 @@ def test_tiled_grid_fixed_supports(s_full, prec):
     """Every fixed support from 3 to 16 has its own gridder kernel (one tap per lane in
     ceil(S^2 / 64) passes); 6 is the largest that fits one pass with lanes to spare, 9 the
     first with two passes, 16 the largest with its own kernel.  With FP32 arithmetic the
-    taps of two records arrive in one load, two adjacent taps per lane; an odd S^2 makes
-    the last pair of a sub-kernel reach one tap beyond it (into the next sub-kernel, or the
-    padding tap after the table)."""
+    taps of two records arrive in one load from a pair-ordered copy of the table; an odd
+    number of taps in the last pass leaves one entry of that copy empty (S = 3, 5, 9)."""
     params = _fixed_params(s_full, prec)
     uvw, vis, wt = _inputs(params, 5)
     G, sw, cnt, host = run_grid(params, uvw, vis, wt)
