@@ -30,6 +30,18 @@ __device__ inline float2 tap_at(const half2c *t, uint32_t i) {
 
 constexpr int kDegridWaves = 4;
 
+// (re, im) += conj(k) m as four fused multiply-adds (written out, because the compiler
+// otherwise forms a product, a fused multiply-add and an add per component)
+__device__ inline float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename Real, typename C2>
+__device__ inline void mac_conj(Real &re, Real &im, Real kx, Real ky, const C2 &m) {
+  re = fma_r(kx, m.x, re);
+  re = fma_r(ky, m.y, re);
+  im = fma_r(kx, m.y, im);
+  im = fma_r(-ky, m.x, im);
+}
+
 // Sum over each aligned group of 8 lanes, valid in the group's first lane: DPP quad
 // permutes pair lanes 1 and 2 apart, then a row shift brings lane +4.
 __device__ inline float dpp_f(float v, int ctrl) {
@@ -140,8 +152,7 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
 #pragma unroll
             for (int ku = 0; ku < S; ++ku) {
               const C2 m = mrow[ku];
-              re += taps[q][ku].x * m.x + taps[q][ku].y * m.y;  // conj(k) * m
-              im += taps[q][ku].x * m.y - taps[q][ku].y * m.x;
+              mac_conj(re, im, taps[q][ku].x, taps[q][ku].y, m);
             }
           }
           re = group8_sum(re);
@@ -172,8 +183,7 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
             for (int ku = 0; ku < Sr; ++ku) {
               const auto k = tap_at(trow, (uint32_t)ku);
               const C2 m = mrow[ku];
-              re += k.x * m.x + k.y * m.y;  // conj(k) * m
-              im += k.x * m.y - k.y * m.x;
+              mac_conj(re, im, (Real)k.x, (Real)k.y, m);
             }
           }
         }
