@@ -11,8 +11,11 @@
 //   scan         exclusive prefix sum of count (Eq. 6);
 //   scatter      record of visibility j goes to offset[key] + slot;
 //   work list    each tile's record range split into chunks of at most `chunk` records.
-// Count atomics are aggregated over runs of a wavefront's lanes that share a key; the
-// scatter recomputes each visibility's key from its coordinates rather than storing it.
+// Count atomics are aggregated over runs of a wavefront's lanes that share a key.  With a
+// fixed support (records carry the packed LDS offset and sub-kernel number) the key pass
+// also stores each visibility's key and packed word next to its slot, so the scatter
+// reads 12 bytes instead of the 24-byte uvw and skips the FP64 footprint; otherwise the
+// scatter recomputes the key from the coordinates.
 #include <algorithm>
 
 #include "wproj_tiled.h"
@@ -63,14 +66,25 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-template <typename Real>
+// The record's first word: LDS offset of the footprint's first cell in its tile's
+// private copy, with the sub-kernel number above it when the records are packed.
+__device__ inline uint32_t record_lds(const Geometry &G, const BinShape &B, const Footprint &f) {
+  const int lx = f.x0 & (B.tile - 1), ly = f.y0 & (B.tile - 1);
+  uint32_t r = (uint32_t)(ly * B.pitch + lx);
+  if (B.pack_sub) r |= (uint32_t)((f.p * G.O + f.ov) * G.O + f.ou) << kLdsBits;
+  return r;
+}
+
+// COMPACT: slots holds three arrays of nvis words: slot, key (kInvalid when the
+// visibility is not gridded) and the record's packed first word.
+template <typename Real, bool COMPACT>
 __global__ void __launch_bounds__(256)
     key_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
                const Real *__restrict__ wt, const int64_t *__restrict__ img_off,
                uint32_t *__restrict__ slots, uint32_t *count,
                double *wsum, unsigned long long *counters) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t key = kInvalid;
+  uint32_t key = kInvalid, packed = 0;
   int cls = kFlagged;
   int img = -1;
   bool clamped = false;
@@ -83,13 +97,20 @@ __global__ void __launch_bounds__(256)
       cls = classify(G, uvw + 3 * j, wj, f);
       if (cls == kGridded) {
         key = bin_key(B, img, f);
+        if constexpr (COMPACT) packed = record_lds(G, B, f);
         w = (double)wj;
         clamped = G.n_w > 1 && fabs(uvw[3 * j + 2]) > G.w_max;
       }
     }
   }
   const uint32_t slot = run_slot(count, key);
-  if (j < nvis) slots[j] = slot;
+  if (j < nvis) {
+    slots[j] = slot;
+    if constexpr (COMPACT) {
+      slots[nvis + j] = key;
+      slots[2 * nvis + j] = packed;
+    }
+  }
   // Counters and weight sums: reduced over the workgroup in LDS, then one atomic per
   // workgroup into one of kSlots partial accumulators (chosen by block index) so that
   // no address is hit by many workgroups; finalize_kernel adds the slots up.  Rows of
@@ -133,28 +154,37 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-template <typename Real, typename Cplx, typename Rec>
+// COMPACT: the key pass stored each visibility's key and packed first word (fixed
+// support S_fix, whose sub-kernel number n starts at tap n S_fix^2).
+template <typename Real, typename Cplx, typename Rec, bool COMPACT>
 __global__ void __launch_bounds__(256)
     scatter_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
                    const Cplx *__restrict__ vis, const Real *__restrict__ wt,
                    const int64_t *__restrict__ img_off, const uint32_t *__restrict__ slots,
-                   const uint32_t *__restrict__ offset, Rec *__restrict__ rec) {
+                   const uint32_t *__restrict__ offset, int S_fix, Rec *__restrict__ rec) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nvis) return;
-  const int img = image_of(img_off, G.n_images, j);
-  if (img < 0) return;
-  // same inputs, same outcome (and key) as the key pass
-  Footprint f;
-  const Real w = wt ? wt[j] : Real(1);
-  if (classify(G, uvw + 3 * j, w, f) != kGridded) return;
-  const uint32_t key = bin_key(B, img, f);
-  const int S = G.supp[f.p];
   Rec r;
-  const int lx = f.x0 & (B.tile - 1), ly = f.y0 & (B.tile - 1);
-  r.lds = (uint32_t)(ly * B.pitch + lx);
-  if (B.pack_sub) r.lds |= (uint32_t)((f.p * G.O + f.ov) * G.O + f.ou) << kLdsBits;
-  r.tap = (uint32_t)(G.tab_off[f.p] + (uint32_t)((f.ov * G.O + f.ou) * S * S)) |
-          ((uint32_t)(S - 1) << kTapBits);
+  uint32_t key;
+  if constexpr (COMPACT) {
+    key = slots[nvis + j];
+    if (key == kInvalid) return;
+    r.lds = slots[2 * nvis + j];
+    r.tap = (r.lds >> kLdsBits) * (uint32_t)(S_fix * S_fix) | ((uint32_t)(S_fix - 1) << kTapBits);
+  } else {
+    const int img = image_of(img_off, G.n_images, j);
+    if (img < 0) return;
+    // same inputs, same outcome (and key) as the key pass
+    Footprint f;
+    const Real w = wt ? wt[j] : Real(1);
+    if (classify(G, uvw + 3 * j, w, f) != kGridded) return;
+    key = bin_key(B, img, f);
+    const int S = G.supp[f.p];
+    r.lds = record_lds(G, B, f);
+    r.tap = (uint32_t)(G.tab_off[f.p] + (uint32_t)((f.ov * G.O + f.ou) * S * S)) |
+            ((uint32_t)(S - 1) << kTapBits);
+  }
+  const Real w = wt ? wt[j] : Real(1);
   if (vis) {
     const Cplx v = vis[j];
     r.wr = w * v.x;
@@ -314,12 +344,21 @@ hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, c
   double *wpart = wsum ? W.wslots : nullptr;
   auto *cnt = counters ? W.cslots : nullptr;
   const dim3 grid(nblk(nvis, 256)), block(256);
+  const bool compact = B.pack_sub != 0;
   if (k->params.precision == WPROJ_F64) {
-    hipLaunchKernelGGL(key_kernel<double>, grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
-                       img_off, W.slots, W.count, wpart, cnt);
+    if (compact)
+      hipLaunchKernelGGL((key_kernel<double, true>), grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
+                         img_off, W.slots, W.count, wpart, cnt);
+    else
+      hipLaunchKernelGGL((key_kernel<double, false>), grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
+                         img_off, W.slots, W.count, wpart, cnt);
   } else {
-    hipLaunchKernelGGL(key_kernel<float>, grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
-                       img_off, W.slots, W.count, wpart, cnt);
+    if (compact)
+      hipLaunchKernelGGL((key_kernel<float, true>), grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
+                         img_off, W.slots, W.count, wpart, cnt);
+    else
+      hipLaunchKernelGGL((key_kernel<float, false>), grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
+                         img_off, W.slots, W.count, wpart, cnt);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (wsum || counters) {
@@ -329,14 +368,25 @@ hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, c
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = launch_exclusive_scan(W.count, W.offset, B.n_keys, W.scan_tmp, s)) != hipSuccess) return e;
+  const int S_fix = k->s_max;
   if (k->params.precision == WPROJ_F64) {
-    hipLaunchKernelGGL((scatter_kernel<double, double2, RecordF64>), grid, block, 0, s, G, B, nvis,
-                       uvw, (const double2 *)vis, (const double *)wt, img_off, W.slots,
-                       W.offset, (RecordF64 *)W.rec);
+    if (compact)
+      hipLaunchKernelGGL((scatter_kernel<double, double2, RecordF64, true>), grid, block, 0, s, G, B, nvis,
+                         uvw, (const double2 *)vis, (const double *)wt, img_off, W.slots, W.offset, S_fix,
+                         (RecordF64 *)W.rec);
+    else
+      hipLaunchKernelGGL((scatter_kernel<double, double2, RecordF64, false>), grid, block, 0, s, G, B, nvis,
+                         uvw, (const double2 *)vis, (const double *)wt, img_off, W.slots, W.offset, S_fix,
+                         (RecordF64 *)W.rec);
   } else {
-    hipLaunchKernelGGL((scatter_kernel<float, float2, RecordF32>), grid, block, 0, s, G, B, nvis,
-                       uvw, (const float2 *)vis, (const float *)wt, img_off, W.slots,
-                       W.offset, (RecordF32 *)W.rec);
+    if (compact)
+      hipLaunchKernelGGL((scatter_kernel<float, float2, RecordF32, true>), grid, block, 0, s, G, B, nvis,
+                         uvw, (const float2 *)vis, (const float *)wt, img_off, W.slots, W.offset, S_fix,
+                         (RecordF32 *)W.rec);
+    else
+      hipLaunchKernelGGL((scatter_kernel<float, float2, RecordF32, false>), grid, block, 0, s, G, B, nvis,
+                         uvw, (const float2 *)vis, (const float *)wt, img_off, W.slots, W.offset, S_fix,
+                         (RecordF32 *)W.rec);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // work list: per tile, ceil(records / chunk) items
