@@ -245,6 +245,9 @@ int64_t carve(const wproj_kernels *k, int64_t nvis, char *base, BinWorkspace &W)
   W.items = (WorkItem *)take((int64_t)sizeof(WorkItem) * max_items);
   W.scan_tmp = (uint32_t *)take(4 * scan_temp_words(std::max(B.n_keys, B.n_tiles)));
   W.counter = (uint32_t *)take(4);
+  W.order = (uint32_t *)take(4 * max_items);
+  W.order_cnt = (uint32_t *)take(4 * 2 * kOrderBuckets);
+  W.max_items = max_items;
   const TileShape ts = tile_shape(k, B.tile);
   const int64_t cplx = k->params.precision == WPROJ_F64 ? 16 : 8;
   W.partial = take(max_items * (int64_t)ts.rows * ts.rows * cplx);
@@ -254,7 +257,7 @@ int64_t carve(const wproj_kernels *k, int64_t nvis, char *base, BinWorkspace &W)
 }
 
 constexpr int kTuneTiles[] = {16, 32};
-constexpr int kTuneChunks[] = {1024, 2048, 4096, 8192};
+constexpr int kTuneChunks[] = {1024, 2048, 4096, 8192, 16384};
 
 bool plane_in_key_for(const wproj_kernels *k, int tile) {
   const int64_t nt = (k->params.n + tile - 1) / tile;

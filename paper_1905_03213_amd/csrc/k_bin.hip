@@ -303,6 +303,57 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Largest-first work order.  The queue of the gridding and degridding kernels hands
+// out work items in this order, so the long items start early and the short ones fill
+// the end of the launch instead of one long item running alone (the work list itself
+// stays in tile order, which the partial-tile reduce relies on).  Items are counted
+// into kOrderBuckets size classes and placed class by class; the order inside a class
+// follows the placement atomics, which changes only the schedule, not any result.
+__device__ inline int size_class(const WorkItem &w, int chunk) {
+  const uint32_t size = w.end - w.begin;  // 1..chunk
+  const uint32_t c = (uint32_t)(((uint64_t)((uint32_t)chunk - size) * kOrderBuckets) / (uint32_t)chunk);
+  return (int)min(c, (uint32_t)(kOrderBuckets - 1));
+}
+
+__global__ void __launch_bounds__(256)
+    order_count_kernel(const WorkItem *__restrict__ items, const uint32_t *__restrict__ n_items_ptr,
+                       int chunk, uint32_t *class_count) {
+  __shared__ uint32_t h[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t n = *n_items_ptr;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&h[size_class(items[i], chunk)], 1u);
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets && h[threadIdx.x]) atomicAdd(&class_count[threadIdx.x], h[threadIdx.x]);
+}
+
+// order[start of class c + cursor] = item; start of class c = items in classes < c.
+__global__ void __launch_bounds__(256)
+    order_place_kernel(const WorkItem *__restrict__ items, const uint32_t *__restrict__ n_items_ptr,
+                       int chunk, const uint32_t *__restrict__ class_count, uint32_t *cursor,
+                       uint32_t *__restrict__ order) {
+  __shared__ uint32_t h[kOrderBuckets], base[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t n = *n_items_ptr;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int c = 0;
+  uint32_t rank = 0;
+  if (i < n) {
+    c = size_class(items[i], chunk);
+    rank = atomicAdd(&h[c], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets) {
+    uint32_t start = 0;
+    for (int k = 0; k < (int)threadIdx.x; ++k) start += class_count[k];
+    base[threadIdx.x] = h[threadIdx.x] ? start + atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]) : 0u;
+  }
+  __syncthreads();
+  if (i < n) order[base[c] + rank] = (uint32_t)i;
+}
+
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -396,6 +447,15 @@ hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, c
   if ((e = launch_exclusive_scan(W.nch, W.choff, B.n_tiles, W.scan_tmp, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(chunk_emit_kernel, dim3(nblk(B.n_tiles, 256)), dim3(256), 0, s, W.offset,
                      B.n_tiles, B.kw, B.chunk, W.choff, W.items);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // largest-first order of the work items (their number is choff[n_tiles] <= max_items)
+  if ((e = launch_fill_u32(W.order_cnt, 2 * kOrderBuckets, 0u, s)) != hipSuccess) return e;
+  const uint32_t *n_items = W.choff + B.n_tiles;
+  hipLaunchKernelGGL(order_count_kernel, dim3(nblk(W.max_items, 256)), dim3(256), 0, s, W.items, n_items,
+                     B.chunk, W.order_cnt);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(order_place_kernel, dim3(nblk(W.max_items, 256)), dim3(256), 0, s, W.items, n_items,
+                     B.chunk, W.order_cnt, W.order_cnt + kOrderBuckets, W.order);
   return hipGetLastError();
 }
 

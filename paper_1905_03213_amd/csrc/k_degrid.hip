@@ -68,7 +68,8 @@ template <typename Real, typename Rec, typename Tab, int S>
 __global__ void __launch_bounds__(64 * kDegridWaves)
     tiled_degrid_kernel(Geometry G, BinShape B, int pitch, int rows, int wave_lds,
                         const Tab *__restrict__ tab, const Rec *__restrict__ rec,
-                        const WorkItem *__restrict__ items, const uint32_t *__restrict__ n_items_ptr,
+                        const WorkItem *__restrict__ items, const uint32_t *__restrict__ order,
+                        const uint32_t *__restrict__ n_items_ptr,
                         uint32_t *counter, const typename Cd<Real>::T *__restrict__ model,
                         typename Cd<Real>::T *__restrict__ out) {
   using C2 = typename Cd<Real>::T;
@@ -86,7 +87,7 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
     if (lane == 0) got = atomicAdd(counter, 1u);
     const uint32_t it = (uint32_t)__builtin_amdgcn_readlane((int)got, 0);
     if (it >= n_items) break;
-    const WorkItem w = items[it];
+    const WorkItem w = items[order[it]];  // largest items first
     const int img = (int)(w.tile / (uint32_t)tiles_per_img);
     const int rt = (int)(w.tile - (uint32_t)img * tiles_per_img);
     const int ty = rt / B.ntx, tx = rt - ty * B.ntx;
@@ -217,7 +218,7 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
   const int wave_lds = (int)(ts.lds_bytes / sizeof(C2));
   hipLaunchKernelGGL(kern, dim3((unsigned)(k->n_cu * per_cu)), dim3(64 * wpb), lds, s, k->geo, B,
                      ts.pitch, ts.rows, wave_lds, (const Tab *)k->d_tab, (const Rec *)W.rec,
-                     W.items, W.choff + B.n_tiles, W.counter, (const C2 *)model, (C2 *)out);
+                     W.items, W.order, W.choff + B.n_tiles, W.counter, (const C2 *)model, (C2 *)out);
   return hipGetLastError();
 }
 

@@ -159,6 +159,7 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
     tiled_grid_kernel(Geometry G, BinShape B, int pitch, int rows, int wave_lds,
                       const Tab *__restrict__ tab, uint32_t tab_bytes,
                       const Rec *__restrict__ rec, const WorkItem *__restrict__ items,
+                      const uint32_t *__restrict__ order,
                       const uint32_t *__restrict__ n_items_ptr, uint32_t *counter,
                       typename Cx<Real>::T *__restrict__ partial,
                       const typename Cx<Real>::T *__restrict__ vis) {
@@ -177,7 +178,8 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
     if (lane == 0) got = atomicAdd(counter, 1u);
     const uint32_t it = (uint32_t)__builtin_amdgcn_readlane((int)got, 0);
     if (it >= n_items) break;
-    const WorkItem w = items[it];
+    const uint32_t item = order[it];  // largest items first
+    const WorkItem w = items[item];
     for (int i = lane; i < area; i += 64) acc[i] = C2{Real(0), Real(0)};
     const uint32_t n_rec = w.end - w.begin;
     // Records arrive 64 at a time with one coalesced load (lane i holds record i of the
@@ -359,7 +361,7 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
 
     // flush: the work item's tile (with halo) goes to its own slot of the partial-tile
     // buffer with plain coalesced stores; tile_reduce_kernel adds the slots to the grid
-    C2 *dst = partial + (size_t)it * rows * rows;
+    C2 *dst = partial + (size_t)item * rows * rows;
     for (int i = lane; i < rows * rows; i += 64) {
       const int ry = i / rows, rx = i - ry * rows;
       dst[i] = acc[ry * pitch + rx];
@@ -428,7 +430,7 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
   const int64_t tab_entries = paired ? n_sub * k->pair_stride : k->n_taps;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, s, k->geo, B, ts.pitch,
                      ts.rows, wave_lds, tab, (uint32_t)(tab_entries * sizeof(Tab)),
-                     (const Rec *)W.rec, W.items, W.choff + B.n_tiles, W.counter,
+                     (const Rec *)W.rec, W.items, W.order, W.choff + B.n_tiles, W.counter,
                      (typename Cx<Real>::T *)W.partial, (const typename Cx<Real>::T *)vis);
   return hipGetLastError();
 }

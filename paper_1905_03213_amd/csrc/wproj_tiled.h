@@ -20,6 +20,10 @@ constexpr uint32_t kLdsMask = (1u << kLdsBits) - 1u;
 constexpr int kMinFixedSupport = 3;
 constexpr int kMaxFixedSupport = 16;
 
+// Size classes of the largest-first work order (class c: items of more than
+// (15 - c) / 16 of a chunk, down to the smallest).
+constexpr int kOrderBuckets = 16;
+
 // Partial accumulators per image (weight sums) and per counter, spread by block index.
 constexpr int kSlots = 256;
 
@@ -90,6 +94,9 @@ struct BinWorkspace {
   WorkItem *items;     // [max_items]
   uint32_t *scan_tmp;  // scan_temp_words(max(n_keys, n_tiles))
   uint32_t *counter;   // [1] work-queue head
+  uint32_t *order;     // [max_items] work-item indices, largest items first
+  uint32_t *order_cnt; // [2 * kOrderBuckets] per size class: item count, placement cursor
+  int64_t max_items;   // capacity of items, order and partial
   void *partial;       // [max_items][rows][rows] complex: each work item's accumulated tile
   double *wslots;      // [n_images][kSlots] partial weight sums
   unsigned long long *cslots;  // [3][kSlots] partial counters
