@@ -193,7 +193,7 @@ int wproj_image(const wproj_kernels *k, int direction, void *grid, void *image,
 
 /*
  * Choose the tiled gridder's tile side (16 or 32 cells) and work-item length (1024 ..
- * 8192 binned records) for this handle by timing each candidate on the caller's data
+ * 16384 binned records) for this handle by timing each candidate on the caller's data
  * (one warm-up and one timed wproj_grid per candidate, HIP events on `stream`), then keep
  * the fastest in the handle.  The choice is also cached per problem shape (grid size,
  * images, planes, supports, oversampling, precision, visibility count rounded to a
@@ -203,7 +203,8 @@ int wproj_image(const wproj_kernels *k, int direction, void *grid, void *image,
  * the handle: no other call may use it concurrently.  The paper attributes the
  * flattening of its scaling curves to workload imbalance between threads and nodes
  * (Sections 3.2, 4); the work-item length is the knob that trades that imbalance
- * against per-item overhead.  Errors: as wproj_grid; WPROJ_EUNSUPPORTED for a handle
+ * against per-item overhead (work items are handed out largest first, so the imbalance
+ * left is mostly that of the last, smallest items).  Errors: as wproj_grid; WPROJ_EUNSUPPORTED for a handle
  * built with WPROJ_ALGO_PLAIN.
  */
 int wproj_autotune(wproj_kernels *k, int64_t nvis, const double *uvw, const void *vis,
