@@ -36,10 +36,10 @@ LDS_BYTES_PER_VIS = S * S * 16   # complex FP32 read-modify-write per tap
 FLOPS_PER_VIS = S * S * 8        # complex multiply-add per tap
 HBM_BYTES_PER_VIS_GRID = 16      # one binned record read by the tile gridder
 # HBM bytes per launch of tiled_grid_kernel from hardware counters (FETCH_SIZE x2.000 +
-# WRITE_SIZE x1.000, scale factors from a 512 MiB copy), measured at tile 32 / 4096
+# WRITE_SIZE x1.000, scale factors from a 512 MiB copy), measured at tile 32 / 8192
 # records per work item on this workload; profiles/tiled_grid_kernel_2048_S8_cfg2.md
 # has the commands and raw values.  Reported only when the run uses that configuration.
-MEASURED_TRAFFIC = {"tile": 32, "chunk": 4096, "bytes": None}  # kernel changed; re-measure
+MEASURED_TRAFFIC = {"tile": 32, "chunk": 8192, "bytes": 1129.1e6}
 
 
 def log(*a):
