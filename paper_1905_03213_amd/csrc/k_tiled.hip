@@ -39,29 +39,16 @@ __device__ inline float2 tab_load(const half2c *t, uint32_t i) {
   return make_float2((float)h.re, (float)h.im);
 }
 
-// Table fetch through a buffer resource: the sub-kernel's first tap is wave-uniform and
-// goes in the scalar offset, the lane's tap in the vector offset, so the address costs
-// no vector instructions.  The hardware range check covers the vector offset only:
-// callers keep the scalar offset inside the table.
-__device__ inline float2 tab_fetch(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t tap, const float2 *) {
-  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, lane * 8u, tap * 8u, 0);
-  // elements are copied out before reinterpretation: a bit cast of a vector element
-  // expression reads the vector's first element
-  const uint32_t re = v[0], im = v[1];
-  return make_float2(__uint_as_float(re), __uint_as_float(im));
-}
+// FP64 table fetch through a buffer resource (one record per load): the sub-kernel's
+// first tap is wave-uniform and goes in the scalar offset, the lane's tap in the vector
+// offset, so the address costs no vector instructions.  The hardware range check covers
+// the vector offset only: callers keep the scalar offset inside the table.
 __device__ inline double2 tab_fetch(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t tap, const double2 *) {
   const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16u, tap * 16u, 0);
   const uint32_t w0 = v[0], w1 = v[1], w2 = v[2], w3 = v[3];
   const uint64_t re = (uint64_t)w0 | ((uint64_t)w1 << 32);
   const uint64_t im = (uint64_t)w2 | ((uint64_t)w3 << 32);
   return make_double2(__longlong_as_double((long long)re), __longlong_as_double((long long)im));
-}
-__device__ inline float2 tab_fetch(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t tap, const half2c *) {
-  const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, lane * 4u, tap * 4u, 0);
-  half2c h;
-  __builtin_memcpy(&h, &v, 4);
-  return make_float2((float)h.re, (float)h.im);
 }
 // gfx9 buffer descriptor word 3: 32-bit data format, no swizzle
 constexpr int kBufferWord3 = 0x00020000;
@@ -288,7 +275,7 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         if (more) cur = nxt;
       }
     } else if constexpr (S > 0) {
-      // Direct-fetch path (fixed support): lane t handles tap t of every record, in
+      // Direct-fetch path (fixed support, FP64): lane t handles tap t of every record, in
       // kPasses passes of 64 taps when S^2 > 64.  Table taps are loaded one group of
       // kGroupS records ahead of their use; the group shrinks as the passes grow, so the
       // prefetched taps stay within a fixed register budget.  (Staging the batch in LDS
