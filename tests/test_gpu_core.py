@@ -87,16 +87,22 @@ def test_plain_grid_multi_image_and_empty_ranges():
     assert np.allclose(sw, swr, rtol=1e-12, atol=0)
 
 
-def test_grid_empty_input_leaves_grid():
+@pytest.mark.parametrize("algo", ["plain", "tiled"])
+def test_grid_empty_input_leaves_grid(algo):
+    """No visibilities: the grid is left as it was and degridding writes nothing (the
+    tiled path then has no records, no work items and an empty work order)."""
     wl = synth.cfg1()
-    params = {**wl.params, "precision": "f32", "algorithm": "plain"}
+    params = {**wl.params, "precision": "f32", "algorithm": algo}
     k = W.make_kernels(params)
     g = k.new_grid() + 1.5
-    W.grid(k, torch.empty((0, 3), dtype=torch.float64, device="cuda"),
-           torch.empty(0, dtype=torch.complex64, device="cuda"),
+    uvw0 = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    W.grid(k, uvw0, torch.empty(0, dtype=torch.complex64, device="cuda"),
            torch.empty(0, dtype=torch.float32, device="cuda"), g)
     torch.cuda.synchronize()
     assert bool((g == 1.5).all())
+    out = torch.empty(0, dtype=torch.complex64, device="cuda")
+    W.degrid(k, uvw0, g, out)
+    torch.cuda.synchronize()
     k.free()
 
 
