@@ -63,9 +63,11 @@ def test_tiled_multi_image(prec):
     assert np.abs(G[1]).max() == 0.0
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_hot_tile_split_into_chunks(prec):
-    # 30000 visibilities inside one 64-cell tile: 4 work items accumulate the same cells.
+@pytest.mark.parametrize("prec,chunk", [("f64", 0), ("f32", 0), ("f32", 1024), ("f32", 16384)])
+def test_hot_tile_split_into_chunks(prec, chunk):
+    # 30000 visibilities inside one 64-cell tile: several work items of different sizes
+    # (30 of 1024 records down to one full and one partial item of 16384) accumulate the
+    # same cells, handed out largest first.
     rng = np.random.default_rng(12)
     wl = synth.cfg1(n_vis=30000)
     fov = wl.params["n"] * wl.params["cell_rad"]
@@ -73,7 +75,7 @@ def test_hot_tile_split_into_chunks(prec):
     th = 2 * np.pi * rng.random(30000)
     uvw = np.stack([r * np.cos(th) + 30.0 / fov, r * np.sin(th) + 30.0 / fov,
                     rng.uniform(-500, 500, 30000)], axis=1)
-    _check({**wl.params, "precision": prec, "algorithm": "tiled"}, uvw, wl.vis, wl.weight)
+    _check({**wl.params, "precision": prec, "algorithm": "tiled", "chunk": chunk}, uvw, wl.vis, wl.weight)
 
 
 def test_autotune_picks_a_candidate_and_keeps_parity():
