@@ -1,8 +1,9 @@
 """Binned gridding and degridding on geometries the other tests do not reach, against
 the FP64 oracle: a single w-plane (w ignored), odd and non-power-of-two oversampling
 (5 and 6, so floor division is not a shift), support 7 with oversampling 4, odd per-plane
-supports, and a grid side that is not a multiple of the tile (ragged edge tiles), each
-with footprints reaching the grid edges."""
+supports, a grid side that is not a multiple of the tile (ragged edge tiles), and more
+sub-kernels than packed records can number (oversampling 256), each with footprints
+reaching the grid edges."""
 
 import numpy as np
 import pytest
@@ -29,6 +30,11 @@ GEOMETRIES = {
                             kernel_image_size=64),
     "ragged_n": dict(n=250, cell_rad=5e-5, n_wplanes=5, w_max=300.0, support=8, oversample=8,
                      kernel_image_size=32),
+    # 5 x 256^2 sub-kernels: more than the 2^18 a record can carry above its LDS offset,
+    # so this fixed support takes unpacked records, the recomputing scatter and the
+    # general gridder and degridder paths
+    "O256_many_subkernels": dict(n=128, cell_rad=6e-5, n_wplanes=5, w_max=300.0, support=4,
+                                 oversample=256, kernel_image_size=32),
 }
 
 
