@@ -15,6 +15,9 @@
  *             x0 = floor((q - S_p O/2)/O) + 1, ou = x0 O - q + S_p O/2 - 1
  *   drop      if a coordinate is non-finite or x0 < 0 or x0 + S_p > N
  *   grid[y0+kv][x0+ku] += W V T_p[ov][ou][kv][ku]
+ * With a Hermitian fold (w_mode 1: planes p dw, dw = w_max/(N_w - 1); w_mode 2: planes
+ * w_max (p/(N_w - 1))^2, nearest in sqrt|w|) a row with w < 0 is taken at (-u, -v, -w)
+ * with conj(V), and degridding returns the conjugate for it.
  * Kernel tables come in as built by the numpy oracle: complex128 interleaved,
  * plane p at tap offset tab_off[p], laid out [ov][ou][kv][ku].
  *
@@ -30,7 +33,7 @@
 #endif
 
 typedef struct {
-  int n, n_w, O;
+  int n, n_w, O, w_mode;
   double fov, w_max, dw;
   const int32_t *supp;
 } plan_t;
@@ -41,9 +44,16 @@ static int64_t floor_div(int64_t a, int64_t b) {
   return q;
 }
 
+/* w is the folded (non-negative) coordinate when w_mode != 0 */
 static int plane_of(const plan_t *P, double w) {
   if (P->n_w == 1) return 0;
-  double t = floor((w + P->w_max) / P->dw + 0.5);
+  double t;
+  if (P->w_mode == 0)
+    t = floor((w + P->w_max) / P->dw + 0.5);
+  else if (P->w_mode == 1)
+    t = floor(w / P->dw + 0.5);
+  else
+    t = floor(sqrt(w / P->w_max) * (double)(P->n_w - 1) + 0.5);
   if (!(t >= 0.0)) return 0; /* also catches NaN */
   if (t > (double)(P->n_w - 1)) return P->n_w - 1;
   return (int)t;
@@ -66,27 +76,37 @@ static int axis_fp(const plan_t *P, double coord, int S, int *x0, int *ou) {
   return 1;
 }
 
-/* 0: gridded; 1: flagged (W == 0); 2: bad weight; 3: dropped. */
+/* 0: gridded; 1: flagged (W == 0); 2: bad weight; 3: dropped.  *fold = 1 when the row
+   is taken at (-u, -v, -w). */
 static int classify(const plan_t *P, const double *uvw, double wt, int *p, int *x0, int *y0,
-                    int *ou, int *ov) {
+                    int *ou, int *ov, int *fold) {
+  *fold = 0;
   if (wt == 0.0) return 1;
   if (!(isfinite(wt) && wt > 0.0)) return 2;
   if (!(isfinite(uvw[0]) && isfinite(uvw[1]) && isfinite(uvw[2]))) return 3;
-  *p = plane_of(P, uvw[2]);
+  double u = uvw[0], v = uvw[1], w = uvw[2];
+  if (P->w_mode != 0 && w < 0.0) {
+    u = -u;
+    v = -v;
+    w = -w;
+    *fold = 1;
+  }
+  *p = plane_of(P, w);
   int S = P->supp[*p];
-  if (!axis_fp(P, uvw[0], S, x0, ou)) return 3;
-  if (!axis_fp(P, uvw[1], S, y0, ov)) return 3;
+  if (!axis_fp(P, u, S, x0, ou)) return 3;
+  if (!axis_fp(P, v, S, y0, ov)) return 3;
   return 0;
 }
 
-static void init_plan(plan_t *P, int n, double cell, int n_w, double w_max,
+static void init_plan(plan_t *P, int n, double cell, int n_w, double w_max, int w_mode,
                       const int32_t *supp, int O) {
   P->n = n;
   P->n_w = n_w;
   P->O = O;
+  P->w_mode = w_mode;
   P->fov = (double)n * cell;
   P->w_max = w_max;
-  P->dw = n_w > 1 ? (2.0 * w_max) / (double)(n_w - 1) : 0.0;
+  P->dw = n_w > 1 ? (w_mode == 0 ? (2.0 * w_max) / (double)(n_w - 1) : w_max / (double)(n_w - 1)) : 0.0;
   P->supp = supp;
 }
 
@@ -95,14 +115,15 @@ static void grid_range(const plan_t *P, const double *tab, const int64_t *tab_of
                        double *G, double *sumw, int64_t *cnt) {
   const int n = P->n, O = P->O;
   for (int64_t j = s; j < e; ++j) {
-    int p, x0, y0, ou, ov;
-    int c = classify(P, uvw + 3 * j, wt[j], &p, &x0, &y0, &ou, &ov);
+    int p, x0, y0, ou, ov, fold;
+    int c = classify(P, uvw + 3 * j, wt[j], &p, &x0, &y0, &ou, &ov, &fold);
     if (c == 2) cnt[2] += 1;
     if (c == 3) cnt[0] += 1;
     if (c != 0) continue;
     if (P->n_w > 1 && fabs(uvw[3 * j + 2]) > P->w_max) cnt[1] += 1;
     const int S = P->supp[p];
-    const double ar = wt[j] * vis[2 * j], ai = wt[j] * vis[2 * j + 1];
+    const double ar = wt[j] * vis[2 * j];
+    const double ai = wt[j] * (fold ? -vis[2 * j + 1] : vis[2 * j + 1]);
     const double *T = tab + 2 * (tab_off[p] + ((int64_t)ov * O + ou) * S * S);
     for (int kv = 0; kv < S; ++kv) {
       double *row = G + 2 * ((int64_t)(y0 + kv) * n + x0);
@@ -123,12 +144,12 @@ static void grid_range(const plan_t *P, const double *tab, const int64_t *tab_of
  * image).  nthreads > 1 uses OpenMP: one image -> private per-thread grids over
  * contiguous row ranges, summed in thread order; several images -> one image per task.
  */
-int wref_grid(int n, double cell, int n_w, double w_max, const int32_t *supp, int O,
+int wref_grid(int n, double cell, int n_w, double w_max, int w_mode, const int32_t *supp, int O,
               const double *tab, const int64_t *tab_off, int64_t nvis, const double *uvw,
               const double *vis, const double *wt, int n_images, const int64_t *img_off,
               double *grid, double *sumw, int64_t *counters, int nthreads) {
   plan_t P;
-  init_plan(&P, n, cell, n_w, w_max, supp, O);
+  init_plan(&P, n, cell, n_w, w_max, w_mode, supp, O);
   const int64_t cells = (int64_t)n * n;
   if (nthreads < 1) nthreads = 1;
   if (n_images > 1 || nthreads == 1) {
@@ -189,12 +210,12 @@ int wref_grid(int n, double cell, int n_w, double w_max, const int32_t *supp, in
  * Degrid: V_j = sum_taps conj(T_p[ov][ou][kv][ku]) M[y0+kv][x0+ku] (complex128
  * interleaved, overwritten); rows with non-finite uvw or off-grid footprints get 0.
  */
-int wref_degrid(int n, double cell, int n_w, double w_max, const int32_t *supp, int O,
+int wref_degrid(int n, double cell, int n_w, double w_max, int w_mode, const int32_t *supp, int O,
                 const double *tab, const int64_t *tab_off, int64_t nvis, const double *uvw,
                 int n_images, const int64_t *img_off, const double *M, double *vis_out,
                 int nthreads) {
   plan_t P;
-  init_plan(&P, n, cell, n_w, w_max, supp, O);
+  init_plan(&P, n, cell, n_w, w_max, w_mode, supp, O);
   const int64_t cells = (int64_t)n * n;
   if (nthreads < 1) nthreads = 1;
   for (int im = 0; im < n_images; ++im) {
@@ -202,9 +223,9 @@ int wref_degrid(int n, double cell, int n_w, double w_max, const int32_t *supp, 
     const double *Mi = M + 2 * cells * im;
 #pragma omp parallel for schedule(static) num_threads(nthreads) if (nthreads > 1)
     for (int64_t j = s; j < e; ++j) {
-      int p, x0, y0, ou, ov;
+      int p, x0, y0, ou, ov, fold = 0;
       double vr = 0.0, vi = 0.0;
-      if (classify(&P, uvw + 3 * j, 1.0, &p, &x0, &y0, &ou, &ov) == 0) {
+      if (classify(&P, uvw + 3 * j, 1.0, &p, &x0, &y0, &ou, &ov, &fold) == 0) {
         const int S = P.supp[p];
         const double *T = tab + 2 * (tab_off[p] + ((int64_t)ov * O + ou) * S * S);
         for (int kv = 0; kv < S; ++kv) {
@@ -218,7 +239,7 @@ int wref_degrid(int n, double cell, int n_w, double w_max, const int32_t *supp, 
         }
       }
       vis_out[2 * j] = vr;
-      vis_out[2 * j + 1] = vi;
+      vis_out[2 * j + 1] = fold ? -vi : vi;
     }
   }
   return 0;

@@ -13,6 +13,13 @@ fixed explicitly:
       arrays are [y][x] row-major with y <-> v <-> m.
   O1  w-planes w_p = -w_max + p dw, dw = 2 w_max/(N_w - 1), plane of w =
       clamp(floor((w + w_max)/dw + 1/2)); a single plane sits at w = 0.
+      Hermitian fold (w_mode "fold" or "fold_sqrt"): a visibility with w < 0 is
+      gridded as conj(V) at (-u, -v, -w), which leaves Re of the image unchanged
+      (the two are Hermitian mirrors), so planes only cover [0, w_max]:
+      "fold": w_p = p dw, dw = w_max/(N_w - 1), plane = clamp(floor(|w|/dw + 1/2));
+      "fold_sqrt": w_p = w_max (p/(N_w - 1))^2, planes evenly spaced in sqrt|w|,
+      plane = clamp(floor(sqrt(|w|/w_max) (N_w - 1) + 1/2)).  Degridding a folded row
+      returns conj of the value degridded at (-u, -v, -w), the real-linear adjoint.
   O2  taper psi = normalised prolate spheroidal function, c = pi S/2 (pswf.py).
   O3  kernel table of plane p: the Fourier transform of psi(l) psi(m) times the
       w phase screen exp(+2 pi i w_p (sqrt(1-l^2-m^2) - 1)), sampled at m x m
@@ -44,6 +51,7 @@ import numpy as np
 from . import pswf
 
 PRECISIONS = ("f64", "f32", "f32_f16table")
+W_MODES = ("linear", "fold", "fold_sqrt")
 
 
 class Plan:
@@ -60,14 +68,24 @@ class Plan:
         self.O = int(params["oversample"])
         self.m = int(params["kernel_image_size"])
         self.n_images = int(params.get("n_images", 1))
+        wm = params.get("w_mode", "linear")
+        self.w_mode = W_MODES[wm] if isinstance(wm, (int, np.integer)) and 0 <= wm < 3 else wm
         self.validate()
         self.fov = float(self.n) * self.cell
-        if self.n_w > 1:
-            self.dw = (2.0 * self.w_max) / float(self.n_w - 1)
-            self.w_planes = np.array([-self.w_max + p * self.dw for p in range(self.n_w)])
-        else:
+        self.fold = self.w_mode != "linear"
+        if self.n_w == 1:
             self.dw = 0.0
             self.w_planes = np.zeros(1)
+        elif self.w_mode == "linear":
+            self.dw = (2.0 * self.w_max) / float(self.n_w - 1)
+            self.w_planes = np.array([-self.w_max + p * self.dw for p in range(self.n_w)])
+        elif self.w_mode == "fold":
+            self.dw = self.w_max / float(self.n_w - 1)
+            self.w_planes = np.array([p * self.dw for p in range(self.n_w)])
+        else:
+            self.dw = 0.0
+            self.w_planes = np.array([self.w_max * (p / float(self.n_w - 1)) ** 2
+                                      for p in range(self.n_w)])
 
     def validate(self):
         n, O = self.n, self.O
@@ -82,6 +100,7 @@ class Plan:
             and 1 <= O <= 256
             and 2 <= self.m <= 4096 and self.m % 2 == 0
             and self.n_images >= 1
+            and self.w_mode in W_MODES
         )
         ok = ok and all(1 <= s <= 32 and s <= n and (s * O) % 2 == 0 for s in self.supports)
         if not ok:
@@ -94,11 +113,17 @@ class Plan:
 
 
 def plane_index(plan: Plan, w: np.ndarray) -> np.ndarray:
-    """O1: nearest plane, rounding half up, clamped to [0, N_w - 1]."""
+    """O1: nearest plane, rounding half up, clamped to [0, N_w - 1].  With a Hermitian
+    fold, w is the folded (non-negative) coordinate."""
     w = np.asarray(w, dtype=np.float64)
     if plan.n_w == 1:
         return np.zeros(w.shape, dtype=np.int64)
-    t = np.floor((w + plan.w_max) / plan.dw + 0.5)
+    if plan.w_mode == "linear":
+        t = np.floor((w + plan.w_max) / plan.dw + 0.5)
+    elif plan.w_mode == "fold":
+        t = np.floor(w / plan.dw + 0.5)
+    else:
+        t = np.floor(np.sqrt(w / plan.w_max) * float(plan.n_w - 1) + 0.5)
     t = np.clip(np.nan_to_num(t, nan=0.0), 0, plan.n_w - 1)
     return t.astype(np.int64)
 
@@ -125,7 +150,8 @@ def axis_footprint(plan: Plan, coord: np.ndarray, supp: np.ndarray):
 def snap(plan: Plan, uvw: np.ndarray, weight: np.ndarray):
     """Per-visibility geometry and validity.
 
-    Returns dict with x0, y0, ou, ov, p (int64 arrays), valid (bool), and the
+    Returns dict with x0, y0, ou, ov, p (int64 arrays), valid (bool), fold (bool: the
+    row was mirrored to (-u, -v, -w) and its visibility is conjugated), and the
     counters [dropped (non-finite uvw or off-grid), w clamped, bad weight].
     """
     uvw = np.asarray(uvw, dtype=np.float64)
@@ -134,15 +160,20 @@ def snap(plan: Plan, uvw: np.ndarray, weight: np.ndarray):
     bad_w = ~flagged & ~(np.isfinite(wt) & (wt > 0.0))
     consider = ~flagged & ~bad_w
     fin = np.isfinite(uvw).all(axis=1)
-    p = plane_index(plan, np.where(fin, uvw[:, 2], 0.0))
+    fold = fin & (uvw[:, 2] < 0.0) if plan.fold else np.zeros(fin.shape, dtype=bool)
+    sgn = np.where(fold, -1.0, 1.0)
+    u = np.where(fin, uvw[:, 0] * sgn, 0.0)
+    v = np.where(fin, uvw[:, 1] * sgn, 0.0)
+    w = np.where(fin, uvw[:, 2] * sgn, 0.0)
+    p = plane_index(plan, w)
     supp = np.asarray(plan.supports, dtype=np.int64)[p]
-    x0, ou, onx = axis_footprint(plan, np.where(fin, uvw[:, 0], 0.0), supp)
-    y0, ov, ony = axis_footprint(plan, np.where(fin, uvw[:, 1], 0.0), supp)
+    x0, ou, onx = axis_footprint(plan, u, supp)
+    y0, ov, ony = axis_footprint(plan, v, supp)
     valid = consider & fin & onx & ony
     dropped = consider & ~valid
     clamped = valid & (np.abs(uvw[:, 2]) > plan.w_max) if plan.n_w > 1 else np.zeros_like(valid)
     counters = np.array([dropped.sum(), clamped.sum(), bad_w.sum()], dtype=np.int64)
-    return dict(x0=x0, y0=y0, ou=ou, ov=ov, p=p, valid=valid, counters=counters)
+    return dict(x0=x0, y0=y0, ou=ou, ov=ov, p=p, valid=valid, fold=fold & valid, counters=counters)
 
 
 def degrid_valid(plan: Plan, uvw: np.ndarray):
@@ -258,7 +289,7 @@ def grid(plan: Plan, tables, uvw, vis, weight, image_offsets=None):
         geo = snap(plan, uvw[s:e], weight[s:e])
         counters += geo["counters"]
         val = geo["valid"]
-        wv = weight[s:e] * vis[s:e]
+        wv = weight[s:e] * np.where(geo["fold"], np.conj(vis[s:e]), vis[s:e])
         sumw[img] = weight[s:e][val].sum()
         for p in np.unique(geo["p"][val]):
             sel = val & (geo["p"] == p)
@@ -286,8 +317,9 @@ def grid_cells(plan: Plan, tables, uvw, vis, weight):
     Returns (cells int64 sorted, values complex128, sumW, counters[3]).
     """
     uvw = np.asarray(uvw, dtype=np.float64)
-    wv = np.asarray(weight, dtype=np.float64) * np.asarray(vis, dtype=np.complex128)
     geo = snap(plan, uvw, weight)
+    vis = np.asarray(vis, dtype=np.complex128)
+    wv = np.asarray(weight, dtype=np.float64) * np.where(geo["fold"], np.conj(vis), vis)
     val = geo["valid"]
     idx, con = [], []
     for p in np.unique(geo["p"][val]):
@@ -377,7 +409,8 @@ def degrid(plan: Plan, tables, uvw, M, image_offsets=None):
                 for ku in range(S):
                     v += np.conj(T[ov, ou, kv, ku]) * M[img, y0 + kv, x0 + ku]
             acc[sel] = v
-        out[s:e] = acc
+        # a folded row was degridded at (-u, -v, -w): its value is the conjugate
+        out[s:e] = np.where(geo["fold"], np.conj(acc), acc)
     return out
 
 

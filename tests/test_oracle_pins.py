@@ -453,3 +453,146 @@ def test_sparse_grid_and_pixel_image_match_dense_forms():
     xs = rng.integers(n // 4, 3 * n // 4, 40)
     pix = R.image_pixels(plan, cells, vals, sw2, ys, xs)
     assert np.abs(pix - img[ys, xs]).max() <= 1e-14 * np.abs(img).max()
+
+
+# --------------------------------------------------------------------------- Hermitian fold
+
+
+def _fold_plan(mode, n_w=5, w_max=100.0):
+    return R.Plan(dict(n=64, cell_rad=1e-3, n_wplanes=n_w, w_max=w_max, support=4, oversample=4,
+                       kernel_image_size=16, w_mode=mode))
+
+
+def test_fold_plane_worked_examples():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "fold_planes.txt"))
+            if l.strip() and not l.startswith("#")]
+    w = np.array([float(r[0]) for r in rows])
+    uvw = np.stack([np.full(len(w), 3.0), np.full(len(w), -2.0), w], axis=1)
+    for col, mode in ((2, "fold"), (3, "fold_sqrt")):
+        plan = _fold_plan(mode)
+        g = R.snap(plan, uvw, np.ones(len(w)))
+        assert g["p"].tolist() == [int(r[col]) for r in rows], mode
+        assert g["fold"].tolist() == [r[1] == "1" for r in rows], mode
+        assert g["counters"][1] == sum(abs(x) > 100.0 for x in w)
+    assert np.allclose(_fold_plan("fold_sqrt").w_planes, [0.0, 6.25, 25.0, 56.25, 100.0], rtol=0, atol=0)
+    assert np.allclose(_fold_plan("fold").w_planes, [0.0, 25.0, 50.0, 75.0, 100.0], rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("mode", ["fold", "fold_sqrt"])
+def test_fold_plane_brute_force(mode):
+    # nearest plane by enumeration: |w| against every plane, distance measured in w
+    # (fold) or in sqrt|w| (fold_sqrt); random w has no ties
+    plan = _fold_plan(mode, n_w=23, w_max=750.0)
+    w = np.random.default_rng(3).uniform(-800.0, 800.0, 5000)
+    a = np.minimum(np.abs(w), plan.w_max)
+    if mode == "fold":
+        d = np.abs(a[:, None] - plan.w_planes[None, :])
+    else:
+        d = np.abs(np.sqrt(a)[:, None] - np.sqrt(plan.w_planes)[None, :])
+    uvw = np.stack([np.zeros_like(w), np.zeros_like(w), w], axis=1)
+    assert R.snap(plan, uvw, np.ones(len(w)))["p"].tolist() == np.argmin(d, axis=1).tolist()
+
+
+def _tie_free(plan, uvw):
+    # drop rows whose snapping is within 5 % of a rounding tie, or whose sub-kernel is the
+    # last one (the half-open table range has no mirror for it), on either side of the
+    # mirror: the mirrored footprint rule is then exactly the mirror of the footprint
+    O = plan.O
+    for ax in (0, 1):
+        g = uvw[:, ax] * plan.fov + plan.n / 2
+        frac = g * O - np.floor(g * O)
+        uvw = uvw[np.abs(frac - 0.5) > 0.05]
+    for s in (1.0, -1.0):
+        geo = R.snap(plan, s * uvw, np.ones(len(uvw)))
+        uvw = uvw[geo["valid"] & (geo["ou"] != O - 1) & (geo["ov"] != O - 1)]
+    return uvw
+
+
+def test_fold_equals_linear_planes_of_the_same_spacing():
+    # "fold" with N planes over [0, w_max] has the spacing of the linear rule with 2N - 1
+    # planes over [-w_max, w_max], whose upper N planes sit at the same w.  Rows with
+    # w >= 0 use the same plane and taps in both; rows with w < 0 are gridded mirrored
+    # and conjugated, which changes the grid but not Re of the image.  So the two images
+    # agree to rounding on rows away from the snapping ties.
+    wl = synth.cfg1w(n_w=9, s_max=7)
+    rng = np.random.default_rng(12)
+    base = dict(wl.params)
+    base.pop("support_per_plane")
+    lin = R.Plan({**base, "n_wplanes": 17, "support": 7, "w_mode": "linear"})
+    fold = R.Plan({**base, "n_wplanes": 9, "support": 7, "w_mode": "fold"})
+    assert np.abs(lin.w_planes[8:] - fold.w_planes).max() < 1e-12
+    uvw = _tie_free(lin, wl.uvw)
+    # keep |w| off the plane-assignment ties of both rules
+    t = np.abs(uvw[:, 2]) / fold.dw
+    uvw = uvw[np.abs(t - np.floor(t) - 0.5) > 0.02]
+    assert (uvw[:, 2] < 0).sum() > 300 and (uvw[:, 2] > 0).sum() > 300
+    vis = rng.standard_normal(len(uvw)) + 1j * rng.standard_normal(len(uvw))
+    wt = rng.uniform(0.5, 2.0, len(uvw))
+    G1, s1, _ = R.grid(lin, R.kernel_tables(lin), uvw, vis, wt)
+    G2, s2, _ = R.grid(fold, R.kernel_tables(fold), uvw, vis, wt)
+    a = R.grid_to_image(lin, G1, s1)[0]
+    b = R.grid_to_image(fold, G2, s2)[0]
+    assert _inner_err(b, a) < 1e-11
+    # and degridding: a folded row's prediction equals the unfolded one (real image)
+    img = rng.standard_normal((lin.n, lin.n))
+    p1 = R.predict(lin, R.kernel_tables(lin), uvw, img)
+    p2 = R.predict(fold, R.kernel_tables(fold), uvw, img)
+    assert np.abs(p2 - p1).max() < 1e-11 * np.abs(p1).max()
+
+
+@pytest.mark.parametrize("mode", ["fold", "fold_sqrt"])
+def test_fold_direct_dft(mode):
+    # the w-dominated tiny field imaged with folded planes over [0, 1000] lambda, supports
+    # growing with w_p from 7 to 12: close to the direct DFT with the w term, and the
+    # error falls as the plane count grows (oversampling 32, so that plane spacing rather
+    # than the snapping to the 1/O lattice dominates)
+    wl = synth.cfg1w(n_w=33, oversample=32)
+    errs = []
+    for n_w in (5, 9, 17):
+        params = {**wl.params, "n_wplanes": n_w, "w_mode": mode}
+        plan0 = R.Plan({**params, "support_per_plane": None})
+        params["support_per_plane"] = [7 + int(math.floor(5 * w / 1000.0 + 0.5)) for w in plan0.w_planes]
+        sub = synth.Workload("f", params, wl.uvw, wl.vis, wl.weight)
+        plan, img = _wproj_image(sub)
+        geo = R.snap(plan, wl.uvw, wl.weight)
+        assert geo["fold"].sum() > 500
+        errs.append(_inner_err(img, _direct_dft_image(plan, wl.uvw, wl.vis, wl.weight, geo["valid"])))
+    print(f"fold {mode}: inner-half error vs the direct DFT {errs}")
+    assert errs[2] < 6e-3
+    assert errs[1] < errs[0] and errs[2] < errs[1]
+
+
+@pytest.mark.parametrize("mode", ["fold", "fold_sqrt"])
+def test_fold_adjoint_identity(mode):
+    # the folded pair is real-linear (conjugation): <Re IDFT(grid W x), y> = Re <x, W A(y)>
+    wl = synth.cfg1w(n_w=17)
+    params = {**wl.params, "w_mode": mode, "n_wplanes": 9, "support_per_plane": None, "support": 7}
+    plan = R.Plan(params)
+    tabs = R.kernel_tables(plan)
+    rng = np.random.default_rng(15)
+    x = rng.standard_normal(wl.nvis) + 1j * rng.standard_normal(wl.nvis)
+    W = rng.uniform(0.5, 2.0, wl.nvis)
+    y = rng.standard_normal((plan.n, plan.n))
+    img = R.grid_to_image(plan, R.grid(plan, tabs, wl.uvw, x, W)[0], None)[0]
+    back = W * R.predict(plan, tabs, wl.uvw, y)
+    lhs = np.sum(img * y)
+    rhs = np.real(np.vdot(x, back))
+    assert abs(lhs - rhs) < 1e-10 * np.linalg.norm(y) * np.linalg.norm(img)
+
+
+@pytest.mark.parametrize("mode", ["fold", "fold_sqrt"])
+def test_c_oracle_matches_numpy_oracle_folded(mode):
+    wl = synth.small_tracks(n=128, n_w=5, support=8, spp=None)
+    uvw = wl.uvw.numpy().copy()
+    uvw[::3, 2] *= -1.0  # plenty of w < 0 rows
+    vis = wl.vis.numpy()
+    wt = np.random.default_rng(4).uniform(0.0, 2.0, wl.nvis)
+    plan = R.Plan({**wl.params, "w_mode": mode})
+    tabs = R.kernel_tables(plan)
+    G, sw, cnt = R.grid(plan, tabs, uvw, vis, wt)
+    Gc, swc, cntc = cref.grid(plan, tabs, uvw, vis, wt, nthreads=4)
+    assert np.abs(Gc - G).max() <= 1e-12 * np.abs(G).max()
+    assert cntc.tolist() == cnt.tolist()
+    M = np.random.default_rng(6).standard_normal((1, plan.n, plan.n)) + 1j
+    assert np.abs(cref.degrid(plan, tabs, uvw, M, nthreads=4)
+                  - R.degrid(plan, tabs, uvw, M)).max() < 1e-12 * np.abs(M).max()
