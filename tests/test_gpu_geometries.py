@@ -83,7 +83,9 @@ def test_tiled_degrid_geometries(geom):
     k.free()
 
 
-FIXED = [3, 4, 5, 6, 9, 12, 16]
+FIXED = list(range(3, 17))
+# supports above 16 have no kernel of their own: the general (one record at a time) path
+GENERAL = [20, 32]
 
 
 def _fixed_params(s_full, prec):
@@ -92,13 +94,15 @@ def _fixed_params(s_full, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f32_f16table"])
-@pytest.mark.parametrize("s_full", FIXED)
+@pytest.mark.parametrize("s_full", FIXED + GENERAL)
 def test_tiled_grid_fixed_supports(s_full, prec):
     """Every fixed support from 3 to 16 has its own gridder kernel (one tap per lane in
     ceil(S^2 / 64) passes); 6 is the largest that fits one pass with lanes to spare, 9 the
     first with two passes, 16 the largest with its own kernel.  With FP32 arithmetic the
     taps of two records arrive in one load from a pair-ordered copy of the table; an odd
-    number of taps in the last pass leaves one entry of that copy empty (S = 3, 5, 9)."""
+    number of taps in the last pass leaves one entry of that copy empty (S = 3, 5, 7, 9,
+    11, 13, 15; 13 and 15 are the three- and four-pass kernels with an odd last pass).
+    Supports 20 and 32 (the largest accepted) take the general path."""
     params = _fixed_params(s_full, prec)
     uvw, vis, wt = _inputs(params, 5)
     G, sw, cnt, host = run_grid(params, uvw, vis, wt)
@@ -108,7 +112,7 @@ def test_tiled_grid_fixed_supports(s_full, prec):
     assert rel_max(G, Gr) <= TOL[prec]
 
 
-@pytest.mark.parametrize("s_full", FIXED)
+@pytest.mark.parametrize("s_full", FIXED + GENERAL)
 def test_tiled_degrid_fixed_supports(s_full):
     params = _fixed_params(s_full, "f32")
     uvw, _, _ = _inputs(params, 6)
