@@ -26,13 +26,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X published peaks and a derived LDS bandwidth (see the roofline notes in the
-# design document): 256 CUs x 128 B/clk x 2.4 GHz.
+# MI355X published peaks.  The LDS figure is the CDNA data-path width (256 CUs x
+# 128 B/clk x 2.4 GHz); the roofline divides by the LDS rate measured on the device
+# (wproj_measure_lds) and reports this figure beside it.  The library is built without
+# packed FP32 instructions, so its FP32 vector peak is half the published 157.3 TFLOP/s.
 PEAK_HBM = 8.0e12
-PEAK_LDS = 256 * 128 * 2.4e9
-PEAK_FP32 = 157.3e12
+PEAK_LDS_SPEC = 256 * 128 * 2.4e9
+PEAK_FP32_PACKED = 157.3e12
+PEAK_FP32 = PEAK_FP32_PACKED / 2
 S = 8
 LDS_BYTES_PER_VIS = S * S * 16   # complex FP32 read-modify-write per tap
+LDS_READ_BYTES_PER_VIS_DEGRID = S * S * 8  # degridding reads one complex FP32 model cell per tap
 FLOPS_PER_VIS = S * S * 8        # complex multiply-add per tap
 HBM_BYTES_PER_VIS_GRID = 16      # one binned record read by the tile gridder
 # HBM bytes per launch of tiled_grid_kernel from hardware counters (FETCH_SIZE x2.000 +
@@ -54,7 +58,12 @@ def parse():
     ap.add_argument("--hours", type=float, default=8.0, help="track length (default: full 8 h)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="work for the OpenMP leg of the host oracle baseline")
+    ap.add_argument("--cpu-single-seconds", type=float, default=10.0,
+                    help="work for the single-thread leg of the host oracle baseline")
+    ap.add_argument("--no-extra-configs", action="store_true",
+                    help="skip timing the 4096^2 variable-support and 64-image workloads")
     ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the step replayed from a captured HIP graph")
     ap.add_argument("--tile", type=int, default=0, help="fix the tile side (skips autotuning)")
@@ -98,6 +107,9 @@ def main():
     if args.sweep:
         sweep(args, dev)
         return
+    lds_rates = measure_lds_peak()
+    peak_lds = max(lds_rates.values())
+    log(f"LDS rate (measured): { {k: round(v / 1e12, 2) for k, v in lds_rates.items()} } TB/s")
     t0 = time.time()
     wl = synth.cfg2(device=dev, precision="f32", hours=args.hours)
     nvis = wl.nvis
@@ -178,20 +190,30 @@ def main():
     log(f"fp32 tiled: {ms_step:.3f} ms/step, {value:.1f} Mvis/s, phases {per}")
 
     t_grid = per["grid"] * 1e-3
+    t_call = (per["bin"] + per["grid"] + per.get("reduce", 0.0)) * 1e-3
     achieved_lds = LDS_BYTES_PER_VIS * n_valid / t_grid
     roofline = {
         "bound": "lds",
         "kernel": "tiled_grid_kernel",
         "achieved": achieved_lds / 1e9,
-        "peak": PEAK_LDS / 1e9,
+        "peak": peak_lds / 1e9,
         "unit": "GB/s",
-        "frac": achieved_lds / PEAK_LDS,
+        "frac": achieved_lds / peak_lds,
         "traffic": (MEASURED_TRAFFIC["bytes"] if (tile, chunk) == (MEASURED_TRAFFIC["tile"],
                                                              MEASURED_TRAFFIC["chunk"]) else None),
+        "peak_source": "measured: wproj_measure_lds, best of 64-bit read / write / read-add-write",
+        "peak_measured_by_mode": {k: v / 1e9 for k, v in lds_rates.items()},
+        "peak_spec": PEAK_LDS_SPEC / 1e9,
+        "kernel_frac": achieved_lds / peak_lds,
+        "kernel_frac_spec": achieved_lds / PEAK_LDS_SPEC,
+        # the whole wproj_grid call (binning + tile gridder + partial-tile reduce)
+        "call_ms": t_call * 1e3,
+        "call_frac": LDS_BYTES_PER_VIS * n_valid / t_call / peak_lds,
         "per_unit": {"unit": "on-grid visibility", "lds_bytes": LDS_BYTES_PER_VIS,
                      "flops": FLOPS_PER_VIS, "hbm_bytes": HBM_BYTES_PER_VIS_GRID},
         "units_per_launch": n_valid,
         "alu_frac": FLOPS_PER_VIS * n_valid / t_grid / PEAK_FP32,
+        "alu_peak_tflops": PEAK_FP32 / 1e12,
         "hbm_frac": HBM_BYTES_PER_VIS_GRID * n_valid / t_grid / PEAK_HBM,
     }
 
@@ -209,6 +231,7 @@ def main():
         dph = k.profile_read()
         k.profile(False)
         degrid_ms = dph["degrid"][0] / max(dph["degrid"][1], 1)
+        degrid_bin_ms = dph["bin"][0] / max(dph["bin"][1], 1)
 
         # a plan: the binning kept, then gridding / degridding of new visibilities on the same
         # rows (an imaging loop's major cycles)
@@ -265,7 +288,10 @@ def main():
              "nvis_total": nvis, "nvis_gridded": n_valid}
     if not args.step_only:
         extra.update({
-            "degrid": {"ms": degrid_ms, "mvis_per_s": n_valid / degrid_ms / 1e3},
+            "degrid": {"ms": degrid_ms, "bin_ms": degrid_bin_ms, "mvis_per_s": n_valid / degrid_ms / 1e3,
+                       "kernel": "tiled_degrid_kernel",
+                       "lds_read_bytes_per_vis": LDS_READ_BYTES_PER_VIS_DEGRID,
+                       "lds_frac": LDS_READ_BYTES_PER_VIS_DEGRID * n_valid / (degrid_ms * 1e-3) / peak_lds},
             "planned": {"grid_ms": planned_grid_ms, "grid_mvis_per_s": n_valid / planned_grid_ms / 1e3,
                         "degrid_ms": planned_degrid_ms},
             "regroup_by_baseline": {"rows": n_t * n_bl, "ms": regroup_ms, "gather_uvw_vis_ms": gather_ms,
@@ -351,9 +377,58 @@ def main():
         del gh, wsh
         kh.free()
 
+    if not args.step_only:
+        # Hermitian fold: rows with w < 0 gridded as conj(V) at (-u, -v, -w), 64 planes over
+        # [0, w_max] (the plane spacing of the 128 linear planes, half the tables), evenly
+        # spaced in w and in sqrt(w)
+        extra["fold"] = {}
+        for mode in ("fold", "fold_sqrt"):
+            kf = W.make_kernels({**params, "n_wplanes": 64, "w_mode": mode, "tile": 0, "chunk": 0})
+            gf = kf.new_grid()
+            wsf = kf.workspace(nvis)
+            tf = W.autotune(kf, uvw, vis32, wt32, workspace=wsf)
+            swf = torch.zeros(1, dtype=torch.float64, device=dev)
+
+            def step_f():
+                gf.zero_()
+                swf.zero_()
+                W.grid(kf, uvw, vis32, wt32, gf, weight_sum=swf, workspace=wsf)
+                W.image(kf, W.GRID_TO_IMAGE, gf, img, swf, workspace=wsf)
+
+            step_f()
+            torch.cuda.synchronize()
+            kf.profile(True)
+            kf.profile_read()
+            ev0.record(stream)
+            for _ in range(args.steps):
+                step_f()
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            msf = ev0.elapsed_time(ev1) / args.steps
+            phf = kf.profile_read()
+            kf.profile(False)
+            tab_bytes = int(kf.export(W._lib.EXPORT_TABLES).numel())
+            extra["fold"][mode] = {
+                "n_wplanes": 64, "ms_per_step": msf, "mvis_per_s": n_valid / msf / 1e3,
+                "phases_ms": {p: v / max(c, 1) for p, (v, c) in phf.items() if c},
+                "table_bytes": tab_bytes, "tuning": {"tile": tf[0], "chunk": tf[1]}}
+            log(f"{mode} (64 planes): {msf:.3f} ms/step, {n_valid / msf / 1e3:.1f} Mvis/s, "
+                f"tables {tab_bytes / 1e6:.1f} MB")
+            del gf, wsf
+            kf.free()
+
+    if not args.step_only and not args.no_extra_configs:
+        del wl, uvw, vis32, wt32, g, img
+        torch.cuda.empty_cache()
+        extra["cfg3"] = time_config("cfg3", dev, args, peak_lds)
+        torch.cuda.empty_cache()
+        extra["cfg4"] = time_config("cfg4", dev, args, peak_lds)
+        torch.cuda.empty_cache()
+        wl = synth.cfg2(device=dev, precision="f32", hours=args.hours)
+
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(wl, args.cpu_seconds)
+        cpu = cpu_baseline(wl, args.cpu_seconds, args.cpu_single_seconds)
         log(f"cpu baseline: {cpu}")
 
     out = {
@@ -427,11 +502,127 @@ def sweep(args, dev):
             k.free()
 
 
-def cpu_baseline(wl, seconds):
-    """The plain C FP64 oracle gridder on the host's cores, on a bounded prefix of the
-    same visibilities, sized to about `seconds` of work."""
-    import numpy as np
+def measure_lds_peak():
+    """The device's LDS data rate (bytes/s) for 64-bit reads, writes and read-add-writes
+    in the gridder's access shape, each the best of three runs."""
+    import paper_1905_03213_amd as W
 
+    rates = {}
+    for mode, name in ((0, "read"), (1, "write"), (2, "read_add_write")):
+        rates[name] = max(W.measure_lds(mode, rounds=4096)[0] for _ in range(3))
+    return rates
+
+
+def time_config(name, dev, args, peak_lds):
+    """One step (zero the grids, wproj_grid, wproj_image) on the 4096^2 variable-support
+    FP16-table workload or the 64-image uneven batch, autotuned, eager and replayed from
+    a HIP graph, with per-phase times and the LDS fraction of the algorithmic
+    read-modify-write bytes (16 B per tap of each gridded visibility)."""
+    import torch
+
+    import paper_1905_03213_amd as W
+    import synth
+
+    t0 = time.time()
+    wl = synth.cfg3(device=dev) if name == "cfg3" else synth.cfg4(device=dev)
+    prec = "f32_f16table" if name == "cfg3" else "f32"
+    params = {**wl.params, "precision": prec, "algorithm": "tiled"}
+    vis = wl.vis.to(torch.complex64)
+    wt = wl.weight.to(torch.float32)
+    off = wl.image_offsets
+    ni = params.get("n_images", 1)
+    k = W.make_kernels(params)
+    ws = k.workspace(wl.nvis)
+    g = k.new_grid()
+    n = params["n"]
+    img = torch.empty((ni, n, n), dtype=torch.float32, device=dev)
+    sw = torch.zeros(ni, dtype=torch.float64, device=dev)
+    tile, chunk = W.autotune(k, wl.uvw, vis, wt, image_offsets=off, workspace=ws)
+    # algorithmic LDS bytes: S_p^2 taps x 16 B for every gridded visibility
+    fp = W.footprints(k, wl.uvw, wt)
+    supp = k.export(W._lib.EXPORT_SUPPORTS).view(torch.int32).to(torch.int64)
+    ok = fp[:, 5] == 0
+    taps = int((supp[fp[:, 4][ok].long()] ** 2).sum().item())
+    del fp
+
+    def step():
+        g.zero_()
+        sw.zero_()
+        W.grid(k, wl.uvw, vis, wt, g, image_offsets=off, weight_sum=sw, workspace=ws)
+        W.image(k, W.GRID_TO_IMAGE, g, img, sw, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    n_valid = int(round(sw.sum().item()))
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    steps = max(3, args.steps // 2)
+    k.profile(True)
+    k.profile_read()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ph = k.profile_read()
+    k.profile(False)
+    per = {p: v / max(c, 1) for p, (v, c) in ph.items() if c}
+    graph_ms = None
+    if args.graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            step()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        graph.replay()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            graph.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        graph_ms = e0.elapsed_time(e1) / steps
+        del graph
+    t_call = per["bin"] + per["grid"] + per.get("reduce", 0.0)
+    lds_bytes = 16 * taps
+    out = {"workload": (f"{name}: {n}^2 x {ni} image(s), {wl.nvis} visibilities, "
+                        f"{params['n_wplanes']} w-planes, supports {min(k.export(W._lib.EXPORT_SUPPORTS).view(torch.int32).tolist())}"
+                        f"..{k.export(W._lib.EXPORT_SUPPORTS).view(torch.int32).max().item()}, {prec}"),
+           "nvis": wl.nvis, "nvis_gridded": n_valid, "ms_per_step": ms, "mvis_per_s": n_valid / ms / 1e3,
+           "graph_replay_ms_per_step": graph_ms, "phases_ms": per, "tuning": {"tile": tile, "chunk": chunk},
+           "mean_taps_per_vis": taps / max(n_valid, 1),
+           "grid_kernel_lds_frac": lds_bytes / (per["grid"] * 1e-3) / peak_lds,
+           "call_lds_frac": lds_bytes / (t_call * 1e-3) / peak_lds}
+    log(f"{name}: {ms:.3f} ms/step, {n_valid / ms / 1e3:.1f} Mvis/s, phases {per}, "
+        f"generated in {time.time() - t0:.1f} s")
+    del ws, g, img
+    k.free()
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(wl, seconds, single_seconds):
+    """The plain C FP64 oracle gridder on the host: OpenMP on every core the process may
+    use, and a single thread (the paper's single-thread reference run, Section 3.1), each
+    on a bounded prefix of the same visibilities sized to about `seconds` of work."""
     from oracle import cref
     from oracle import wproj_ref as R
 
@@ -439,26 +630,34 @@ def cpu_baseline(wl, seconds):
     tabs = R.kernel_tables(plan)
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     threads = max(1, min(threads, int(os.environ.get("OMP_NUM_THREADS", threads))))
-    # calibrate on a prefix (after one untimed warm-up call), then size the timed sample
-    n0 = 2_000_000
-    u = wl.uvw[:n0].cpu().numpy()
-    v = wl.vis[:n0].cpu().numpy()
-    w = wl.weight[:n0].cpu().numpy()
-    cref.grid(plan, tabs, u[:10000], v[:10000], w[:10000], nthreads=threads)
-    t = time.time()
-    cref.grid(plan, tabs, u, v, w, nthreads=threads)
-    rate = n0 / max(time.time() - t, 1e-3)
-    ns = int(min(wl.nvis, max(n0, rate * seconds)))
-    u = wl.uvw[:ns].cpu().numpy()
-    v = wl.vis[:ns].cpu().numpy()
-    w = wl.weight[:ns].cpu().numpy()
-    t = time.time()
-    _, sw, _ = cref.grid(plan, tabs, u, v, w, nthreads=threads)
-    dt = time.time() - t
-    return {"value": float(sw[0]) / dt / 1e6, "unit": "Mvis/s", "cores": threads, "kind": "oracle",
+
+    def leg(nthreads, secs, n0):
+        # calibrate on a prefix (after one untimed warm-up call), then size the timed sample
+        u = wl.uvw[:n0].cpu().numpy()
+        v = wl.vis[:n0].cpu().numpy()
+        w = wl.weight[:n0].cpu().numpy()
+        cref.grid(plan, tabs, u[:10000], v[:10000], w[:10000], nthreads=nthreads)
+        t = time.time()
+        cref.grid(plan, tabs, u, v, w, nthreads=nthreads)
+        rate = n0 / max(time.time() - t, 1e-3)
+        ns = int(min(wl.nvis, max(n0, rate * secs)))
+        u = wl.uvw[:ns].cpu().numpy()
+        v = wl.vis[:ns].cpu().numpy()
+        w = wl.weight[:ns].cpu().numpy()
+        t = time.time()
+        _, sw, _ = cref.grid(plan, tabs, u, v, w, nthreads=nthreads)
+        dt = time.time() - t
+        return float(sw[0]) / dt / 1e6, ns, dt
+
+    val, ns, dt = leg(threads, seconds, 2_000_000)
+    val1, ns1, dt1 = leg(1, single_seconds, 200_000)
+    return {"value": val, "unit": "Mvis/s", "cores": threads, "kind": "oracle",
             "sample": (f"{'all' if ns == wl.nvis else 'first ' + str(ns) + ' of'} {wl.nvis} "
                        f"visibilities (MS order), FP64 C oracle gridder, OpenMP per-thread grids, "
-                       f"{dt:.1f} s")}
+                       f"{dt:.1f} s"),
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": val1, "unit": "Mvis/s", "cores": 1,
+                              "sample": f"first {ns1} of {wl.nvis} visibilities, {dt1:.1f} s"}}
 
 
 if __name__ == "__main__":

@@ -51,13 +51,22 @@ typedef enum {
 } wproj_algorithm;
 
 typedef enum {
+  WPROJ_W_LINEAR = 0,    /* N_w planes at w_p = -w_max + p 2 w_max/(N_w - 1) */
+  WPROJ_W_FOLD = 1,      /* Hermitian fold: a row with w < 0 is gridded as conj(V) at
+                            (-u, -v, -w); planes at w_p = p w_max/(N_w - 1) cover [0, w_max] */
+  WPROJ_W_FOLD_SQRT = 2  /* Hermitian fold with planes w_p = w_max (p/(N_w - 1))^2, evenly
+                            spaced in sqrt(w); nearest plane in sqrt(|w|/w_max) (N_w - 1) */
+} wproj_w_mode;
+
+typedef enum {
   WPROJ_OK = 0,
   WPROJ_EINVAL = -1,       /* invalid argument or parameter block */
   WPROJ_ENOMEM = -2,       /* device allocation failed (wproj_make_kernels only) */
   WPROJ_EHIP = -3,         /* a HIP runtime call failed */
   WPROJ_EUNSUPPORTED = -4, /* valid but not supported by this build (message says why) */
   WPROJ_EWORKSPACE = -5,   /* workspace smaller than wproj_workspace_size() */
-  WPROJ_EFFT = -6          /* rocFFT plan creation or execution failed */
+  WPROJ_EFFT = -6,         /* rocFFT plan creation or execution failed */
+  WPROJ_EEMPTY = -7        /* an image has no gridded weight (sum of weights 0): wproj_check_weights */
 } wproj_status;
 
 /*
@@ -70,7 +79,7 @@ typedef enum {
  */
 typedef struct {
   int32_t n;                /* grid/image side N: even, 2..32768 */
-  int32_t n_wplanes;        /* N_w >= 1: planes at w_p = -w_max + p 2 w_max/(N_w-1); one plane = w 0 */
+  int32_t n_wplanes;        /* N_w >= 1: planes as w_mode sets them; one plane = w 0 */
   double cell_rad;          /* image cell (radians) > 0, with n * cell_rad < 2 */
   double w_max;             /* >= 0 (> 0 when N_w > 1), wavelengths */
   int32_t support;          /* S: full support in cells of the w = 0 kernel, 1..32; also sets the
@@ -85,7 +94,12 @@ typedef struct {
   int32_t tile;             /* tiled gridder tile side: 0 = default (16), else 16, 32 or 64 */
   int32_t chunk;            /* tiled gridder work-item length in records: 0 = default (2048),
                                else 256..65536 */
-  int32_t reserved[4];      /* must be zero */
+  int32_t w_mode;           /* wproj_w_mode (0 = linear planes over [-w_max, w_max]).  The fold
+                               halves the planes (and tables) needed for a given plane spacing:
+                               with a real sky V(-u,-v,-w) = conj(V(u,v,w)), so Re of the image
+                               is unchanged.  The paper's own imager uses planes over the full
+                               w range (Section 3.1: 23 w-planes); the fold is a variant. */
+  int32_t reserved[3];      /* must be zero */
 } wproj_params;
 
 typedef struct wproj_kernels wproj_kernels; /* opaque handle */
@@ -159,8 +173,10 @@ int wproj_grid(const wproj_kernels *k, int64_t nvis, const double *uvw, const vo
                int64_t *counters, void *workspace, int64_t workspace_bytes, void *stream);
 
 /*
- * Degridding, the adjoint of gridding (prediction of model visibilities).  With
- * WPROJ_ALGO_TILED the visibilities are binned as for gridding and each tile of the
+ * Degridding, the adjoint of gridding (prediction of model visibilities from a model
+ * grid; the paper names gridding and degridding together as the steps earlier GPU and
+ * Cell imagers accelerated, Section 2, and its imager's CLEAN cycles predict from the
+ * model this way).  With WPROJ_ALGO_TILED the visibilities are binned as for gridding and each tile of the
  * model grid is read once into LDS; WPROJ_ALGO_PLAIN gathers straight from HBM:
  *   vis_out[j] = sum_{kv,ku} conj(T_p[ov][ou][kv][ku]) model_grid[i][y0+kv][x0+ku]
  * with the same footprint rule; rows with non-finite uvw or off-grid footprints, and
@@ -185,14 +201,29 @@ typedef enum {
  * (the paper's final IFFT, Sections 2.1-2.2; rocFFT does the 2D transforms).
  * GRID_TO_IMAGE*: grid is transformed IN PLACE (its contents are destroyed) and
  * image is written.  IMAGE_TO_GRID: image is read and grid is overwritten.
- * weight_sum (float64 [n_images], device) is read only by GRID_TO_IMAGE.
+ * weight_sum (float64 [n_images], device) is read only by GRID_TO_IMAGE; an image
+ * whose sum is 0 is written as zeros (see wproj_check_weights).
  * Errors: WPROJ_EINVAL, WPROJ_EWORKSPACE, WPROJ_EFFT.
  */
 int wproj_image(const wproj_kernels *k, int direction, void *grid, void *image,
                 const double *weight_sum, void *workspace, int64_t workspace_bytes, void *stream);
 
 /*
- * Choose the tiled gridder's tile side (16 or 32 cells) and work-item length (1024 ..
+ * The empty-image status.  GRID_TO_IMAGE divides by weight_sum[i] (natural weighting;
+ * the paper does not spell out the normalisation of its images, Section 3.1 compares
+ * them by noise and peak flux).  An image that received no gridded visibility has
+ * weight_sum[i] == 0; wproj_image cannot report that, because it only enqueues work
+ * and the sums live on the device, so it writes that image as all zeros (0 instead of
+ * a division by 0) and returns WPROJ_OK.  wproj_check_weights waits for `stream`,
+ * reads the n_images sums (device, float64) and returns WPROJ_EEMPTY, naming the first
+ * such image in wproj_last_error(), if any sum is 0, WPROJ_EINVAL if any is negative
+ * or not finite, else WPROJ_OK.  Synchronises `stream`.  Errors: WPROJ_EINVAL, WPROJ_EHIP.
+ */
+int wproj_check_weights(const wproj_kernels *k, const double *weight_sum, void *stream);
+
+/*
+ * Choose the tiled gridder's tile side (16, 32 or 64 cells, each where one wavefront's
+ * tile copy with its halo fits in a workgroup's LDS) and work-item length (1024 ..
  * 16384 binned records) for this handle by timing each candidate on the caller's data
  * (one warm-up and one timed wproj_grid per candidate, HIP events on `stream`), then keep
  * the fastest in the handle.  The choice is also cached per problem shape (grid size,
@@ -272,10 +303,12 @@ int wproj_degrid_planned(const wproj_plan *plan, const void *model_grid, void *v
  * takes, exported.  For visibility j, out[6 j .. 6 j + 5] (int32, device) =
  * {x0, y0, ou, ov, p, class}: first footprint cell (x0, y0), sub-kernel (ou, ov), w-plane
  * p, and class 0 = gridded, 1 = flagged (weight 0), 2 = weight negative or non-finite,
- * 3 = dropped (non-finite uvw or footprint off the grid).  With
+ * 3 = dropped (non-finite uvw or footprint off the grid), 4 = gridded at the Hermitian
+ * mirror (-u, -v, -w) with conj(V) (w < 0 under a folding w_mode; the footprint given is
+ * that of the mirrored point).  With
  *   g = u FoV + n/2, q = floor(g O + 1/2), x0 = floor((q - S O/2)/O) + 1,
  *   ou = x0 O - q + S O/2 - 1  (the same for v, y0, ov),
- *   p = nearest plane of w, ties up, clamped to [0, n_wplanes - 1]  (S = S_p),
+ *   p = nearest plane of w, ties up, clamped to [0, n_wplanes - 1]  (S = S_p; see w_mode),
  * every product and sum rounded separately in float64.  Rows of class != 0 carry -1
  * for x0 .. p.  weight: float64 for WPROJ_F64, float32 otherwise, nullable (all 1).
  * Errors: WPROJ_EINVAL, WPROJ_EHIP.
@@ -317,6 +350,20 @@ int wproj_regroup_rows(int64_t n_rows, const int32_t *ant1, const int32_t *ant2,
  */
 int wproj_gather_rows(int64_t n_rows, int64_t row_bytes, const int64_t *perm, int64_t n_src_rows,
                       const void *src, void *dst, int64_t *bad, void *stream);
+
+/*
+ * Measurement aid, not part of imaging: the device's LDS data rate for the access
+ * shape of the tile gridder's private tiles (each lane its own 8-byte word, 64
+ * consecutive words per instruction, 8 independent accesses in flight per lane, every
+ * CU filled with workgroups).  mode 0 = 64-bit reads, 1 = 64-bit writes, 2 = 64-bit
+ * read, add and write of the same word.  Runs the streaming kernel once untimed and
+ * once between HIP events on `stream`, waits, and writes the aggregate bytes per
+ * second (and, if ms is not NULL, the kernel time in ms) to host memory.  rounds
+ * (1..2^20) sets the work: each lane moves rounds x 64 bytes (x 2 in mode 2).
+ * Allocates and frees a small output buffer.  Errors: WPROJ_EINVAL, WPROJ_ENOMEM,
+ * WPROJ_EHIP.
+ */
+int wproj_measure_lds(int mode, int32_t rounds, double *bytes_per_second, double *ms, void *stream);
 
 /* Message describing the last non-OK status returned on the calling thread ("" if none). */
 const char *wproj_last_error(void);

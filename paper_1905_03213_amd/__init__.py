@@ -17,6 +17,7 @@ from .wproj import (  # noqa: F401
     Plan,
     WprojError,
     autotune,
+    check_weights,
     degrid,
     footprints,
     gather_rows,
@@ -24,6 +25,7 @@ from .wproj import (  # noqa: F401
     image,
     last_error,
     make_kernels,
+    measure_lds,
     regroup_rows,
     version,
 )

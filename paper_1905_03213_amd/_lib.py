@@ -12,18 +12,19 @@ LIB_PATH = os.path.join(HERE, "libwproj.so")
 
 F64, F32, F32_F16TABLE = 0, 1, 2
 ALGO_TILED, ALGO_PLAIN = 0, 1
+W_LINEAR, W_FOLD, W_FOLD_SQRT = 0, 1, 2
 GRID_TO_IMAGE, IMAGE_TO_GRID, GRID_TO_IMAGE_RAW = 0, 1, 2
 EXPORT_TABLES, EXPORT_TABLE_OFFSETS, EXPORT_KAPPA, EXPORT_TAPER, EXPORT_SUPPORTS = range(5)
 
 STATUS = {0: "WPROJ_OK", -1: "WPROJ_EINVAL", -2: "WPROJ_ENOMEM", -3: "WPROJ_EHIP",
-          -4: "WPROJ_EUNSUPPORTED", -5: "WPROJ_EWORKSPACE", -6: "WPROJ_EFFT"}
+          -4: "WPROJ_EUNSUPPORTED", -5: "WPROJ_EWORKSPACE", -6: "WPROJ_EFFT", -7: "WPROJ_EEMPTY"}
 
 EXPORTED = ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_workspace_size",
             "wproj_grid", "wproj_degrid", "wproj_image", "wproj_autotune", "wproj_tuning",
             "wproj_profile", "wproj_profile_read", "wproj_last_error", "wproj_version",
             "wproj_footprints", "wproj_regroup_workspace_size", "wproj_regroup_rows",
             "wproj_gather_rows", "wproj_plan_create", "wproj_plan_free", "wproj_grid_planned",
-            "wproj_degrid_planned")
+            "wproj_degrid_planned", "wproj_check_weights", "wproj_measure_lds")
 PHASES = ("bin", "grid", "plain", "fft", "correct", "degrid", "reduce")
 
 
@@ -42,7 +43,8 @@ class Params(ctypes.Structure):
         ("algorithm", ctypes.c_int32),
         ("tile", ctypes.c_int32),
         ("chunk", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("w_mode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -89,11 +91,13 @@ def lib():
     L.wproj_regroup_workspace_size.restype = i64
     L.wproj_regroup_rows.argtypes = [i64, vp, vp, ctypes.c_int32, vp, vp, vp, vp, i64, vp]
     L.wproj_gather_rows.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp]
+    L.wproj_check_weights.argtypes = [vp, vp, vp]
+    L.wproj_measure_lds.argtypes = [i32, ctypes.c_int32, vp, vp, vp]
     for name in ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_grid",
                  "wproj_degrid", "wproj_image", "wproj_autotune", "wproj_tuning", "wproj_profile",
                  "wproj_profile_read", "wproj_version", "wproj_footprints", "wproj_regroup_rows",
                  "wproj_gather_rows", "wproj_plan_create", "wproj_plan_free", "wproj_grid_planned",
-                 "wproj_degrid_planned"):
+                 "wproj_degrid_planned", "wproj_check_weights", "wproj_measure_lds"):
         getattr(L, name).restype = i32
     _lib = L
     return L

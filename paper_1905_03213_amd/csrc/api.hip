@@ -139,6 +139,8 @@ int validate(const wproj_params *p, std::vector<int32_t> &supp) {
     return fail(WPROJ_EINVAL, "tile must be 0, 16, 32 or 64");
   if (p->chunk != 0 && (p->chunk < 256 || p->chunk > 65536))
     return fail(WPROJ_EINVAL, "chunk must be 0 or in [256, 65536]");
+  if (p->w_mode < WPROJ_W_LINEAR || p->w_mode > WPROJ_W_FOLD_SQRT)
+    return fail(WPROJ_EINVAL, "unknown w_mode %d", p->w_mode);
   for (int r : p->reserved)
     if (r != 0) return fail(WPROJ_EINVAL, "reserved fields must be zero");
   supp.assign(p->n_wplanes, p->support);
@@ -222,6 +224,12 @@ BinShape bin_shape(const wproj_kernels *k) {
   return B;
 }
 
+// Bins the 32-bit keys can number: with a Hermitian fold the key pass keeps the fold
+// flag of fixed-support records in the key's top bit.
+int64_t max_keys(const wproj_kernels *k) {
+  return k->params.w_mode != WPROJ_W_LINEAR ? (int64_t)0x7fffffffll : (int64_t)0xffffffffll;
+}
+
 // Lays the binning buffers out from `base` (nullptr: sizes only); returns total bytes.
 int64_t carve(const wproj_kernels *k, int64_t nvis, char *base, BinWorkspace &W) {
   const BinShape B = bin_shape(k);
@@ -256,7 +264,11 @@ int64_t carve(const wproj_kernels *k, int64_t nvis, char *base, BinWorkspace &W)
   return off;
 }
 
-constexpr int kTuneTiles[] = {16, 32};
+// Tile sides the autotuner tries (each only where one wavefront's tile copy fits in a
+// workgroup's LDS).  128 is not offered: a 128-cell tile with its halo needs more than
+// the 64 KiB a workgroup may hold (146 KB at S = 8 in FP32) and more cells than the
+// records' 14-bit LDS offset can address.
+constexpr int kTuneTiles[] = {16, 32, 64};
 constexpr int kTuneChunks[] = {1024, 2048, 4096, 8192, 16384};
 
 bool plane_in_key_for(const wproj_kernels *k, int tile) {
@@ -273,6 +285,7 @@ int64_t workspace_bytes_for(const wproj_kernels *k, int64_t nvis) {
     tmp.s_max = k->s_max;
     tmp.uniform_support = k->uniform_support;
     for (int tile : kTuneTiles) {
+      if (tile_shape(k, tile).lds_bytes + 256 > k->max_lds) continue;  // never tuned to
       tmp.tile = tile;
       tmp.plane_in_key = plane_in_key_for(k, tile);
       tmp.chunk = kTuneChunks[0];
@@ -286,11 +299,12 @@ int64_t workspace_bytes_for(const wproj_kernels *k, int64_t nvis) {
 }
 
 struct TuneKey {
-  int n, n_images, n_w, s_max, uniform, O, precision;
+  int n, n_images, n_w, s_max, uniform, O, precision, w_mode;
   int log2_nvis;
   bool operator<(const TuneKey &o) const {
-    return std::tie(n, n_images, n_w, s_max, uniform, O, precision, log2_nvis) <
-           std::tie(o.n, o.n_images, o.n_w, o.s_max, o.uniform, o.O, o.precision, o.log2_nvis);
+    return std::tie(n, n_images, n_w, s_max, uniform, O, precision, w_mode, log2_nvis) <
+           std::tie(o.n, o.n_images, o.n_w, o.s_max, o.uniform, o.O, o.precision, o.w_mode,
+                    o.log2_nvis);
   }
 };
 std::mutex g_tune_mu;
@@ -299,6 +313,8 @@ std::map<TuneKey, std::pair<int, int>> g_tune_cache;
 }  // namespace
 
 namespace wproj {
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
 PhaseTimer::PhaseTimer(const wproj_kernels *kc, int ph, hipStream_t st)
     : k(const_cast<wproj_kernels *>(kc)), phase(ph), s(st) {
   if (!k->profiling) return;
@@ -406,9 +422,12 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
   G.log2_O = -1;
   for (int b = 0; b < 9; ++b)
     if ((1 << b) == O) G.log2_O = b;
+  G.w_mode = params->w_mode;
   G.fov = (double)n * params->cell_rad;
   G.w_max = params->w_max;
-  G.dw = n_w > 1 ? (2.0 * params->w_max) / (double)(n_w - 1) : 0.0;
+  G.dw = 0.0;
+  if (n_w > 1 && G.w_mode == WPROJ_W_LINEAR) G.dw = (2.0 * params->w_max) / (double)(n_w - 1);
+  if (n_w > 1 && G.w_mode == WPROJ_W_FOLD) G.dw = params->w_max / (double)(n_w - 1);
 
   if (hipMalloc(&k->d_supp, sizeof(int32_t) * n_w) != hipSuccess ||
       hipMalloc(&k->d_tab_off, sizeof(int64_t) * (n_w + 1)) != hipSuccess ||
@@ -440,7 +459,8 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
   HIP_TRY(hipMalloc(&tmp.p[3], (size_t)batch * so_max * so_max * 16));
   for (int p0 = 0; p0 < n_w; p0 += batch) {
     const int np = std::min(batch, n_w - p0);
-    HIP_TRY(launch_screen(k->d_taper, m, G.fov, G.w_max, G.dw, n_w, p0, np, (double2 *)tmp.p[1], s));
+    HIP_TRY(launch_screen(k->d_taper, m, G.fov, G.w_max, G.dw, n_w, G.w_mode, p0, np,
+                          (double2 *)tmp.p[1], s));
     HIP_TRY(launch_table_dft((const double2 *)tmp.p[1], m, O, k->d_supp, p0, np, so_max,
                              (double2 *)tmp.p[2], (double2 *)tmp.p[3], s));
     HIP_TRY(launch_normalise((const double2 *)tmp.p[3], so_max, O, k->d_supp, k->d_tab_off, p0, np,
@@ -561,7 +581,7 @@ int wproj_grid(const wproj_kernels *k, int64_t nvis, const double *uvw, const vo
     return fail(WPROJ_EUNSUPPORTED, "kernel tables of %lld taps exceed the tiled gridder's 2^26",
                 (long long)k->n_taps);
   const BinShape B = bin_shape(k);
-  if (B.n_keys >= (int64_t)0xffffffffll)
+  if (B.n_keys >= max_keys(k))
     return fail(WPROJ_EUNSUPPORTED, "%lld bins (images x tiles) exceed the tiled gridder's 32-bit keys",
                 (long long)B.n_keys);
   BinWorkspace W;
@@ -599,7 +619,8 @@ int wproj_autotune(wproj_kernels *k, int64_t nvis, const double *uvw, const void
   int lg = 0;
   while (lg < 62 && (1ll << (lg + 1)) <= std::max<int64_t>(nvis, 1)) ++lg;
   const TuneKey key{k->params.n, k->params.n_images, k->params.n_wplanes, k->s_max,
-                    k->uniform_support ? 1 : 0, k->params.oversample, k->params.precision, lg};
+                    k->uniform_support ? 1 : 0, k->params.oversample, k->params.precision,
+                    k->params.w_mode, lg};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -695,7 +716,7 @@ int wproj_degrid(const wproj_kernels *k, int64_t nvis, const double *uvw, const 
     return fail(WPROJ_EUNSUPPORTED, "kernel tables of %lld taps exceed the tiled degridder's 2^26",
                 (long long)k->n_taps);
   const BinShape B = bin_shape(k);
-  if (B.n_keys >= (int64_t)0xffffffffll)
+  if (B.n_keys >= max_keys(k))
     return fail(WPROJ_EUNSUPPORTED, "%lld bins (images x tiles) exceed the tiled degridder's 32-bit keys",
                 (long long)B.n_keys);
   BinWorkspace W;
@@ -754,6 +775,25 @@ int wproj_image(const wproj_kernels *k, int direction, void *grid, void *image,
   return WPROJ_OK;
 }
 
+int wproj_check_weights(const wproj_kernels *k, const double *weight_sum, void *stream) {
+  g_err.clear();
+  if (!k) return fail(WPROJ_EINVAL, "handle is NULL");
+  if (!weight_sum) return fail(WPROJ_EINVAL, "weight_sum is NULL");
+  int rc = check_device(k);
+  if (rc != WPROJ_OK) return rc;
+  const int ni = k->params.n_images;
+  std::vector<double> h(ni);
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  HIP_TRY(hipMemcpy(h.data(), weight_sum, sizeof(double) * ni, hipMemcpyDeviceToHost));
+  for (int i = 0; i < ni; ++i)
+    if (!(isfinite(h[i]) && h[i] >= 0.0))
+      return fail(WPROJ_EINVAL, "weight_sum[%d] = %g is negative or not finite", i, h[i]);
+  for (int i = 0; i < ni; ++i)
+    if (h[i] == 0.0)
+      return fail(WPROJ_EEMPTY, "image %d has no gridded weight (weight_sum 0): its image is all zeros", i);
+  return WPROJ_OK;
+}
+
 }  // extern "C"
 
 // A binning kept for repeated gridding / degridding of the same rows.
@@ -792,7 +832,7 @@ int wproj_plan_create(const wproj_kernels *k, int64_t nvis, const double *uvw, c
   p->k = k;
   p->nvis = nvis;
   p->B = bin_shape(k);
-  if (p->B.n_keys >= (int64_t)0xffffffffll) {
+  if (p->B.n_keys >= max_keys(k)) {
     const long long n_keys = (long long)p->B.n_keys;
     delete p;
     return fail(WPROJ_EUNSUPPORTED, "%lld bins exceed the tiled path's 32-bit keys", n_keys);

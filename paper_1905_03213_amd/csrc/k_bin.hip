@@ -24,6 +24,7 @@ namespace wproj {
 namespace {
 
 constexpr uint32_t kInvalid = 0xffffffffu;
+constexpr uint32_t kFoldBit = 0x80000000u;
 
 __device__ inline uint64_t lane_mask_lt() {
   const int lane = threadIdx.x & 63;
@@ -87,7 +88,7 @@ __global__ void __launch_bounds__(256)
   uint32_t key = kInvalid, packed = 0;
   int cls = kFlagged;
   int img = -1;
-  bool clamped = false;
+  bool clamped = false, fold = false;
   double w = 0.0;
   if (j < nvis) {
     img = image_of(img_off, G.n_images, j);
@@ -97,6 +98,7 @@ __global__ void __launch_bounds__(256)
       cls = classify(G, uvw + 3 * j, wj, f);
       if (cls == kGridded) {
         key = bin_key(B, img, f);
+        fold = f.fold;
         if constexpr (COMPACT) packed = record_lds(G, B, f);
         w = (double)wj;
         clamped = G.n_w > 1 && fabs(uvw[3 * j + 2]) > G.w_max;
@@ -107,7 +109,9 @@ __global__ void __launch_bounds__(256)
   if (j < nvis) {
     slots[j] = slot;
     if constexpr (COMPACT) {
-      slots[nvis + j] = key;
+      // a Hermitian-folded visibility keeps its flag in the key's top bit (keys then stay
+      // below 2^31)
+      slots[nvis + j] = fold ? (key | kFoldBit) : key;
       slots[2 * nvis + j] = packed;
     }
   }
@@ -166,9 +170,12 @@ __global__ void __launch_bounds__(256)
   if (j >= nvis) return;
   Rec r;
   uint32_t key;
+  bool fold;
   if constexpr (COMPACT) {
     key = slots[nvis + j];
     if (key == kInvalid) return;
+    fold = (key & kFoldBit) != 0;
+    key &= ~kFoldBit;
     r.lds = slots[2 * nvis + j];
     r.tap = (r.lds >> kLdsBits) * (uint32_t)(S_fix * S_fix) | ((uint32_t)(S_fix - 1) << kTapBits);
   } else {
@@ -178,6 +185,7 @@ __global__ void __launch_bounds__(256)
     Footprint f;
     const Real w = wt ? wt[j] : Real(1);
     if (classify(G, uvw + 3 * j, w, f) != kGridded) return;
+    fold = f.fold;
     key = bin_key(B, img, f);
     const int S = G.supp[f.p];
     r.lds = record_lds(G, B, f);
@@ -186,11 +194,13 @@ __global__ void __launch_bounds__(256)
   }
   const Real w = wt ? wt[j] : Real(1);
   if (vis) {
+    // a folded visibility enters conjugated
     const Cplx v = vis[j];
     r.wr = w * v.x;
-    r.wi = w * v.y;
+    r.wi = (fold ? -w : w) * v.y;
   } else {
-    set_plan(r, w, (uint32_t)j);
+    // row-carrying records mark a folded row by a negative weight
+    set_plan(r, fold ? -w : w, (uint32_t)j);
   }
   rec[offset[key] + slots[j]] = r;
 }

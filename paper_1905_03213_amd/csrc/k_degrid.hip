@@ -81,6 +81,7 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
   const uint32_t n_items = *n_items_ptr;
   const int64_t cells = (int64_t)G.n * G.n;
   const int tiles_per_img = B.ntx * B.nty;
+  const bool folding = G.w_mode != WPROJ_W_LINEAR;
 
   for (;;) {
     uint32_t got = 0;
@@ -119,11 +120,14 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
         const uint32_t i = b + (uint32_t)lane;
         dst = rec[w.begin + (i < n_rec ? i : n_rec - 1)];  // padding lanes repeat the last record
       };
-      auto fetch = [&](const Rec &c, int t, C2 *tap_row, uint32_t &tb_out, int &base_out, uint32_t &row_out) {
+      auto fetch = [&](const Rec &c, int t, C2 *tap_row, uint32_t &tb_out, int &base_out, uint32_t &row_out,
+                       bool &fold_out) {
         const int j = t * 8 + grp;
         const uint32_t tp = (uint32_t)__shfl((int)c.tap, j, 64);
         base_out = __shfl((int)c.lds, j, 64) & (int)kLdsMask;
         row_out = (uint32_t)__shfl((int)get_row(c), j, 64);
+        // a Hermitian-folded row (negative weight in its record) predicts the conjugate
+        fold_out = folding && __shfl(c.wr, j, 64) < Real(0);
         tb_out = tp & kTapMask;
         const uint32_t kv = r < S ? (uint32_t)r : 0u;
 #pragma unroll
@@ -142,11 +146,12 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
         C2 taps[2][S];
         uint32_t tb[2], row[2];
         int base[2];
-        fetch(cur, 0, taps[0], tb[0], base[0], row[0]);
+        bool fl[2];
+        fetch(cur, 0, taps[0], tb[0], base[0], row[0], fl[0]);
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
           const int q = t & 1;
-          if (t + 1 < 8) fetch(cur, t + 1, taps[q ^ 1], tb[q ^ 1], base[q ^ 1], row[q ^ 1]);
+          if (t + 1 < 8) fetch(cur, t + 1, taps[q ^ 1], tb[q ^ 1], base[q ^ 1], row[q ^ 1], fl[q ^ 1]);
           Real re = 0, im = 0;
           if (r < S) {
             const C2 *mrow = tile + base[q] + r * pitch;
@@ -162,7 +167,7 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
           if (r == 0 && jr < n_rec) {
             C2 o;
             o.x = re;
-            o.y = im;
+            o.y = fl[q] ? -im : im;
             out[row[q]] = o;
           }
         }
@@ -193,7 +198,7 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
         if (r == 0 && valid) {
           C2 o;
           o.x = re;
-          o.y = im;
+          o.y = rr.wr < Real(0) ? -im : im;  // a Hermitian-folded row predicts the conjugate
           out[get_row(rr)] = o;
         }
       }

@@ -1,8 +1,10 @@
 // Plain gridder and degridder: no binning, every tap goes straight to the grid in HBM
-// with a global atomic add (gridding) or a gather (degridding).  This is the direct
-// form of the paper's GPU gridding step (Section 2.2: threads over convolution taps,
-// atomic writes to global memory) and serves as the comparison path for the tiled
-// gridder; in FP64 it is the double-precision baseline.
+// with a global atomic add (gridding) or a gather (degridding).  This is a per-tap
+// atomic baseline, not the paper's GPU gridder: that one (Section 2.2) also spreads
+// threads over convolution taps with atomic writes to global memory, but each thread
+// first sums consecutive timestamps of one baseline in a register and writes only when
+// the baseline changes.  It serves as the comparison path for the tiled gridder; in
+// FP64 it is the double-precision baseline.
 //
 // One 64-lane wavefront owns a contiguous range of visibilities and handles them one
 // at a time, its lanes covering the S_p x S_p taps (64 at a time).
@@ -51,7 +53,7 @@ __global__ void __launch_bounds__(256)
     }
     wacc += (double)w;
     const Cplx v = vis[j];
-    const Real ar = w * v.x, ai = w * v.y;
+    const Real ar = w * v.x, ai = (f.fold ? -w : w) * v.y;  // a folded row enters conjugated
     const int S = G.supp[f.p];
     const Tab *T = tab + G.tab_off[f.p] + ((int64_t)f.ov * G.O + f.ou) * S * S;
     Real *gimg = grid + 2 * cells * img;
@@ -96,10 +98,12 @@ __global__ void __launch_bounds__(256)
   for (int64_t jb = j0; jb < j1; jb += 8) {
     const int64_t j = jb + grp;
     Real re = 0, im = 0;
+    bool fold = false;
     if (j < j1) {
       const int img = image_of(img_off, G.n_images, j);
       Footprint f;
       if (img >= 0 && classify(G, uvw + 3 * j, 1.0, f) == kGridded) {
+        fold = f.fold;
         const int S = G.supp[f.p];
         const Tab *T = tab + G.tab_off[f.p] + ((int64_t)f.ov * G.O + f.ou) * S * S;
         const Cplx *gimg = grid + cells * img;
@@ -124,7 +128,7 @@ __global__ void __launch_bounds__(256)
     if (r == 0 && j < j1) {
       Cplx o;
       o.x = re;
-      o.y = im;
+      o.y = fold ? -im : im;  // a Hermitian-folded row predicts the conjugate
       out[j] = o;
     }
   }
@@ -214,7 +218,7 @@ __global__ void __launch_bounds__(256)
   o[2] = on ? f.ou : -1;
   o[3] = on ? f.ov : -1;
   o[4] = on ? f.p : -1;
-  o[5] = cls;
+  o[5] = on && f.fold ? kGriddedFolded : cls;
 }
 
 }  // namespace

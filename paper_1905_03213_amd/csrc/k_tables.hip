@@ -50,14 +50,26 @@ __global__ void taper_kernel(const double *coef, int n_coef, int m, int n, doubl
 }
 
 __global__ void screen_kernel(const double *taper, int m, double fov, double w_max, double dw,
-                              int n_w, int p0, int np, double2 *out) {
+                              int n_w, int w_mode, int p0, int np, double2 *out) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t total = (int64_t)np * m * m;
   if (t >= total) return;
   int i = (int)(t % m);
   int j = (int)((t / m) % m);
   int p = p0 + (int)(t / ((int64_t)m * m));
-  double wp = n_w > 1 ? -w_max + p * dw : 0.0;
+  // plane values: linear over [-w_max, w_max], or over [0, w_max] with a Hermitian fold
+  // (evenly spaced in w, or in sqrt(w))
+  double wp = 0.0;
+  if (n_w > 1) {
+    if (w_mode == WPROJ_W_LINEAR) {
+      wp = -w_max + p * dw;
+    } else if (w_mode == WPROJ_W_FOLD) {
+      wp = p * dw;
+    } else {
+      const double f = (double)p / (double)(n_w - 1);
+      wp = w_max * (f * f);
+    }
+  }
   double lmax = fov / 2.0;
   double li = (2.0 * i + 1.0 - m) / (double)m * lmax;
   double mj = (2.0 * j + 1.0 - m) / (double)m * lmax;
@@ -199,10 +211,10 @@ hipError_t launch_taper(const double *d_coef, int n_coef, int m, int n, double *
 }
 
 hipError_t launch_screen(const double *d_taper, int m, double fov, double w_max, double dw,
-                         int n_w, int p0, int np, double2 *out, hipStream_t s) {
+                         int n_w, int w_mode, int p0, int np, double2 *out, hipStream_t s) {
   int64_t total = (int64_t)np * m * m;
   hipLaunchKernelGGL(screen_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, d_taper, m,
-                     fov, w_max, dw, n_w, p0, np, out);
+                     fov, w_max, dw, n_w, w_mode, p0, np, out);
   return hipGetLastError();
 }
 

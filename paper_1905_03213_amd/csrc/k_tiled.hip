@@ -2,10 +2,13 @@
 // wavefront owns the work item and accumulates its records in a private LDS copy of
 // the tile plus an (S_max - 1)-cell halo on the high-x / high-y sides, then stores the
 // copy to the work item's slot of a partial-tile buffer; tile_reduce_kernel adds the
-// slots to the grid, one thread per cell in a fixed order (no atomics, deterministic).
+// slots to the grid, one thread per cell in a fixed order (no atomics; the sum over the
+// partial tiles does not depend on scheduling, though the order of records inside a bin,
+// and so the FP32 rounding inside a partial tile, follows the binning's count atomics).
 // The read-modify-write traffic of gridding therefore stays in LDS instead of going to
-// HBM (the paper's CUDA gridder updates the grid in global memory with atomics for every
-// tap of every visibility, Section 2.2).
+// HBM (the paper's CUDA gridder, Section 2.2, keeps one thread per kernel tap and
+// baseline, sums that baseline's consecutive timestamps in a register and writes to the
+// grid in global memory with an atomic add when it moves to the next baseline).
 //
 // Because the tile is private to one wavefront and its 64 lanes always touch 64
 // distinct cells of a record's footprint, the accumulation is a plain LDS read, add and
@@ -119,12 +122,13 @@ template <> struct Cx<double> { using T = double2; };
 constexpr int kGroup = 8;
 constexpr int kMaxWavesPerBlock = 4;
 
-// A row-carrying record (weight, row) turned into W V from the visibility it names.
+// A row-carrying record (weight, row) turned into W V from the visibility it names; a
+// negative weight marks a Hermitian-folded row, which enters as W conj(V).
 template <typename Rec, typename C2>
 __device__ inline void to_weighted(Rec &r, const C2 *vis) {
   const C2 v = vis[get_row(r)];
   const auto wgt = r.wr;
-  r.wr = wgt * v.x;
+  r.wr = fabs(wgt) * v.x;
   r.wi = wgt * v.y;
 }
 

@@ -26,17 +26,22 @@ struct Geometry {
   int32_t n_w;      // w-planes
   int32_t n_images;
   int32_t log2_O;   // log2(O) when O is a power of two, else -1
+  int32_t w_mode;   // wproj_w_mode: linear over [-w_max, w_max], or a Hermitian fold
   double fov;       // n * cell_rad
   double w_max;
-  double dw;        // 2 w_max / (n_w - 1), 0 for a single plane
+  double dw;        // plane spacing: 2 w_max / (n_w - 1) (linear), w_max / (n_w - 1) (fold),
+                    // 0 for a single plane or the square-root spacing
   const int32_t *supp;     // device [n_w] full support per plane
   const int64_t *tab_off;  // device [n_w + 1] first tap of each plane
 };
 
 enum VisClass { kGridded = 0, kFlagged = 1, kBadWeight = 2, kDropped = 3 };
+// wproj_footprints only: gridded at the Hermitian mirror (-u, -v, -w)
+constexpr int kGriddedFolded = 4;
 
 struct Footprint {
   int x0, y0, ou, ov, p;
+  bool fold;  // taken at (-u, -v, -w): the visibility enters conjugated
 };
 
 // floor(a / b) for b > 0
@@ -46,11 +51,19 @@ __device__ inline int floor_div32(int a, int b) {
   return q;
 }
 
-// Nearest w-plane, ties rounding up, clamped to [0, n_w - 1].
+// Nearest w-plane, ties rounding up, clamped to [0, n_w - 1].  With a Hermitian fold w
+// is the folded coordinate |w|: planes p dw (WPROJ_W_FOLD), or w_max (p / (n_w - 1))^2,
+// nearest in sqrt(|w| / w_max) (WPROJ_W_FOLD_SQRT).
 __device__ inline int plane_of(const Geometry &G, double w) {
 #pragma clang fp contract(off)
   if (G.n_w == 1) return 0;
-  double t = floor((w + G.w_max) / G.dw + 0.5);
+  double t;
+  if (G.w_mode == WPROJ_W_LINEAR)
+    t = floor((w + G.w_max) / G.dw + 0.5);
+  else if (G.w_mode == WPROJ_W_FOLD)
+    t = floor(w / G.dw + 0.5);
+  else
+    t = floor(sqrt(w / G.w_max) * (double)(G.n_w - 1) + 0.5);
   if (!(t >= 0.0)) return 0;
   if (t > (double)(G.n_w - 1)) return G.n_w - 1;
   return (int)t;
@@ -85,8 +98,16 @@ template <typename WT>
 __device__ inline int classify(const Geometry &G, const double *uvw, WT wt, Footprint &f) {
   if (wt == WT(0)) return kFlagged;
   if (!(isfinite((double)wt) && wt > WT(0))) return kBadWeight;
-  const double u = uvw[0], v = uvw[1], w = uvw[2];
+  double u = uvw[0], v = uvw[1], w = uvw[2];
   if (!(isfinite(u) && isfinite(v) && isfinite(w))) return kDropped;
+  // Hermitian fold: V(-u, -v, -w) = conj(V(u, v, w)) for a real sky, so a row with w < 0
+  // is gridded as conj(V) at the mirrored point and the planes only cover w >= 0
+  f.fold = G.w_mode != WPROJ_W_LINEAR && w < 0.0;
+  if (f.fold) {
+    u = -u;
+    v = -v;
+    w = -w;
+  }
   f.p = plane_of(G, w);
   const int S = G.supp[f.p];
   if (!axis_footprint(G, u, S, f.x0, f.ou)) return kDropped;
@@ -160,6 +181,9 @@ struct PhaseTimer {
 
 namespace wproj {
 
+// Sets the calling thread's wproj_last_error() message and returns code.
+int set_error(int code, const char *msg);
+
 // ---- launchers (each returns hipSuccess or the first launch error) ----
 
 // Table generation (FP64): taper/kappa evaluation from Legendre coefficients of psi_0.
@@ -167,7 +191,7 @@ hipError_t launch_taper(const double *d_coef, int n_coef, int m, int n, double *
                         double *d_kappa, hipStream_t s);
 // Screen for planes [p0, p0 + np): out[p - p0][j][i] complex128.
 hipError_t launch_screen(const double *d_taper, int m, double fov, double w_max, double dw,
-                         int n_w, int p0, int np, double2 *out, hipStream_t s);
+                         int n_w, int w_mode, int p0, int np, double2 *out, hipStream_t s);
 // Row and column DFTs for planes [p0, p0 + np) into C[p - p0][ib][ia], stride so_max.
 hipError_t launch_table_dft(const double2 *screen, int m, int O, const int32_t *d_supp, int p0,
                             int np, int so_max, double2 *tmp, double2 *C, hipStream_t s);

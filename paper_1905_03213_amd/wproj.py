@@ -18,6 +18,7 @@ from ._lib import (ALGO_PLAIN, ALGO_TILED, F32, F32_F16TABLE, F64, GRID_TO_IMAGE
 
 _PREC = {"f64": F64, "f32": F32, "f32_f16table": F32_F16TABLE}
 _ALGO = {"tiled": ALGO_TILED, "plain": ALGO_PLAIN}
+_WMODE = {"linear": _lib.W_LINEAR, "fold": _lib.W_FOLD, "fold_sqrt": _lib.W_FOLD_SQRT}
 
 
 def _stream(stream):
@@ -109,7 +110,8 @@ class Kernels:
 def make_kernels(params: dict, stream=None) -> Kernels:
     """wproj_make_kernels.  params keys: n, cell_rad, n_wplanes, w_max, support,
     support_per_plane (list or None), oversample, kernel_image_size, precision
-    ("f64" | "f32" | "f32_f16table"), n_images, algorithm ("tiled" | "plain"), tile, chunk."""
+    ("f64" | "f32" | "f32_f16table"), n_images, algorithm ("tiled" | "plain"), tile, chunk,
+    w_mode ("linear" | "fold" | "fold_sqrt")."""
     P = _lib.Params()
     P.n = int(params["n"])
     P.n_wplanes = int(params["n_wplanes"])
@@ -130,6 +132,8 @@ def make_kernels(params: dict, stream=None) -> Kernels:
     P.algorithm = _ALGO[algo] if isinstance(algo, str) else int(algo)
     P.tile = int(params.get("tile", 0))
     P.chunk = int(params.get("chunk", 0))
+    wm = params.get("w_mode", "linear")
+    P.w_mode = _WMODE[wm] if isinstance(wm, str) else int(wm)
     h = ctypes.c_void_p()
     _lib.check("wproj_make_kernels",
                _lib.lib().wproj_make_kernels(ctypes.byref(P), _stream(stream), ctypes.byref(h)))
@@ -157,6 +161,23 @@ def grid(k: Kernels, uvw: torch.Tensor, vis: torch.Tensor, weight: torch.Tensor,
         _ptr(weight_sum, "weight_sum", torch.float64, ni),
         _ptr(counters, "counters", torch.int64, 3),
         _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
+
+
+def check_weights(k: Kernels, weight_sum: torch.Tensor, stream=None):
+    """wproj_check_weights: waits for the stream; raises WprojError (code WPROJ_EEMPTY = -7)
+    when an image's sum of weights is 0 (that image comes out of GRID_TO_IMAGE as zeros)."""
+    ni = k.params.get("n_images", 1)
+    _lib.check("wproj_check_weights", _lib.lib().wproj_check_weights(
+        k.handle, _ptr(weight_sum, "weight_sum", torch.float64, ni), _stream(stream)))
+
+
+def measure_lds(mode: int, rounds: int = 4096, stream=None) -> tuple:
+    """wproj_measure_lds: (bytes per second, kernel ms) of the LDS streaming kernel
+    (mode 0 reads, 1 writes, 2 read-add-write of 64-bit words)."""
+    bps, ms = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _lib.check("wproj_measure_lds", _lib.lib().wproj_measure_lds(
+        int(mode), int(rounds), ctypes.byref(bps), ctypes.byref(ms), _stream(stream)))
+    return bps.value, ms.value
 
 
 def autotune(k: Kernels, uvw: torch.Tensor, vis: torch.Tensor, weight: torch.Tensor,

@@ -57,6 +57,16 @@ def rel_rms(a, b):
     return float(np.sqrt(np.mean(np.abs(d) ** 2)) / np.abs(np.asarray(b)).max())
 
 
+def grad_bound(pred_err_rms, r_rms, base):
+    """Error bound of an FP32 chi^2 gradient relative to its peak.  The gradient
+    -2 kappa kappa Re IDFT(grid(W r)) is linear in the residual r = V_obs - A(I), so the
+    FP32 prediction's error dA enters as a residual error of relative size
+    rms|dA| / rms|r|; r and dA are both noise-like over the rows, so their images scale
+    alike, with a factor 3 for max against rms.  The backward pass (FP32 gridding and
+    transform) adds at most the FP32 gridding tolerance `base`."""
+    return base + 3.0 * pred_err_rms / r_rms
+
+
 def planted(wl, seed=0, n_bad=7):
     """Copies of a workload's arrays with random weights and planted special rows:
     zero weights, a negative and a NaN weight, non-finite uvw, an off-grid row."""

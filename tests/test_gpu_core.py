@@ -12,7 +12,7 @@ import paper_1905_03213_amd as W
 import synth
 from oracle import wproj_ref as R
 
-from gpu_util import CDT, RDT, oracle_grid, planted, rel_max, run_grid
+from gpu_util import CDT, RDT, as_gpu_inputs, oracle_grid, planted, rel_max, run_grid
 
 pytestmark = pytest.mark.gpu
 
@@ -174,4 +174,40 @@ def test_unit_point_source_images_to_delta_centre():
     img = torch.empty((1, n, n), dtype=torch.float64, device="cuda")
     W.image(k, W.GRID_TO_IMAGE, g, img, sw)
     assert abs(img[0, n // 2, n // 2].item() - 1.0) < 1e-12
+    k.free()
+
+
+@pytest.mark.parametrize("algo", ["tiled", "plain"])
+def test_empty_image_is_zero_and_reported(algo):
+    """An image that receives no gridded weight (every weight 0 here, or every row of
+    image 1 flagged) comes out of GRID_TO_IMAGE as zeros, and wproj_check_weights reports
+    WPROJ_EEMPTY for it; images with weight pass."""
+    wl = synth.cfg1w(n_w=9, s_max=10)
+    offs = np.array([0, 600, 1200, 2000])
+    params = {**wl.params, "precision": "f32", "algorithm": algo, "n_images": 3}
+    k = W.make_kernels(params)
+    n = params["n"]
+    wt = np.ones(len(wl.vis))
+    wt[600:1200] = 0.0  # image 1: all flagged
+    (u, v, w), _ = as_gpu_inputs(wl.uvw, wl.vis, wt, "f32")
+    off = torch.as_tensor(offs, dtype=torch.int64).cuda()
+    g = k.new_grid()
+    sw = torch.zeros(3, dtype=torch.float64, device="cuda")
+    W.grid(k, u, v, w, g, image_offsets=off, weight_sum=sw)
+    img = torch.full((3, n, n), 7.0, dtype=torch.float32, device="cuda")
+    W.image(k, W.GRID_TO_IMAGE, g, img, sw)
+    with pytest.raises(W.WprojError) as ei:
+        W.check_weights(k, sw)
+    assert ei.value.code == -7 and "image 1" in str(ei.value)
+    got = img.cpu().numpy()
+    assert sw.cpu().tolist()[1] == 0.0
+    assert not np.any(got[1])
+    assert np.all(np.isfinite(got)) and np.abs(got[0]).max() > 0 and np.abs(got[2]).max() > 0
+    # every image with weight: OK
+    sw2 = torch.ones(3, dtype=torch.float64, device="cuda")
+    W.check_weights(k, sw2)
+    sw2[2] = float("nan")
+    with pytest.raises(W.WprojError) as ei:
+        W.check_weights(k, sw2)
+    assert ei.value.code == -1
     k.free()

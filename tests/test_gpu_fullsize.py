@@ -23,7 +23,7 @@ import synth
 from oracle import cref
 from oracle import wproj_ref as R
 
-from gpu_util import rel_max, rel_rms
+from gpu_util import grad_bound, rel_max, rel_rms
 
 pytestmark = pytest.mark.gpu
 
@@ -151,4 +151,76 @@ def test_cfg5_full_degrid():
     e = rel_max(got, ref)
     _report("cfg5 f32 degrid", vis_max=e, vis_rms=rel_rms(got, ref), nvis=wl.nvis)
     assert e <= 1e-5
+    k.free()
+
+
+def test_cfg5_full_chi2_gradient():
+    """chi^2 gradient of the 2048^2 FP32 model over 1.01e7 visibilities against the
+    oracle's adjoint (O9: -2 kappa kappa Re IDFT(grid(W r)), with the C oracle for the
+    gridding and degridding), at I = 0 and at a perturbed image, plus central differences
+    through the GPU path (chi^2 is quadratic in I, so they carry no truncation error)."""
+    from paper_1905_03213_amd.autograd import chi2
+
+    wl = synth.cfg5(device="cuda")
+    n = wl.params["n"]
+    q = n // 4
+    inner = (slice(q, n - q), slice(q, n - q))
+    plan = R.Plan({**wl.params, "precision": "f64"})
+    tabs = R.kernel_tables(plan)
+    uvw_h = wl.uvw.cpu().numpy()
+    truth = synth.cfg5_model_image(n)
+    rng = np.random.default_rng(55)
+    v_true = cref.degrid(plan, tabs, uvw_h, R.image_to_grid(plan, truth[None]), nthreads=THREADS)
+    Vo = torch.as_tensor(v_true, device="cuda") + wl.vis  # plus the workload's noise (sigma 0.01)
+    Vo = Vo.to(torch.complex64)
+    Wt = torch.as_tensor(rng.uniform(0.5, 2.0, wl.nvis), dtype=torch.float32, device="cuda")
+    vo_h = Vo.to(torch.complex128).cpu().numpy()
+    wt_h = Wt.double().cpu().numpy()
+    k = W.make_kernels({**wl.params, "precision": "f32", "algorithm": "tiled"})
+    U = wl.uvw
+    kap = R.kappa(plan)
+    for name, img0 in (("zero", np.zeros((n, n))), ("perturbed", 0.9 * truth)):
+        img32 = img0.astype(np.float32)
+        I = torch.tensor(img32, device="cuda", requires_grad=True)
+        loss = chi2(I, k, U, Vo, Wt)
+        loss.backward()
+        got = I.grad.double().cpu().numpy()
+        # oracle: r = V_obs - A(I) in FP64 from the same FP32 image and FP32-rounded V_obs
+        a_ref = cref.degrid(plan, tabs, uvw_h, R.image_to_grid(plan, img32.astype(np.float64)[None]),
+                            nthreads=THREADS)
+        r = vo_h - a_ref
+        G, _, _ = cref.grid(plan, tabs, uvw_h, r, wt_h, nthreads=THREADS)
+        ref = -2.0 * R.grid_to_image(plan, G, None)[0]
+        del G
+        with torch.no_grad():
+            from paper_1905_03213_amd.autograd import predict
+            a_gpu = predict(I, k, U).to(torch.complex128).cpu().numpy()
+        d_rms = float(np.sqrt(np.mean(np.abs(a_gpu - a_ref) ** 2)))
+        r_rms = float(np.sqrt(np.mean(np.abs(r) ** 2)))
+        bound = grad_bound(d_rms, r_rms, 1e-5)
+        e_max = rel_max(got[inner], ref[inner])
+        e_rms = rel_rms(got[inner], ref[inner])
+        _report(f"cfg5 chi2 gradient at {name}", grad_max=e_max, grad_rms=e_rms, bound=bound,
+                pred_err_rms=d_rms, resid_rms=r_rms, nvis=wl.nvis)
+        assert e_max <= bound, (e_max, bound)
+        assert abs(loss.item() - float(np.sum(wt_h * np.abs(r) ** 2))) <= 1e-4 * loss.item()
+        # central differences at a few inner pixels: chi^2(I +- h e) computed by the GPU path.
+        # Each chi^2 carries the FP32 prediction error: |d chi^2| <= 2 sqrt(sum W^2 |r|^2) rms|dA|
+        # (a sum of 1e7 independent terms) with r the residual at I +- h e, 4 sigma margin.
+        h = 1.0
+        for _ in range(3):
+            y, x = (int(v) for v in rng.integers(q, n - q, 2))
+            e = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+            e[y, x] = h
+            with torch.no_grad():
+                fp = chi2(I + e, k, U, Vo, Wt).item()
+                fm = chi2(I - e, k, U, Vo, Wt).item()
+            fd = (fp - fm) / (2 * h)
+            # |A(h e)| per row is about h kappa(x) kappa(y) (taps normalised to sum 1)
+            hk = h * kap[x] * kap[y]
+            r_h = np.sqrt(np.sum(wt_h ** 2 * (np.abs(r) ** 2 + hk * hk)))
+            tol = 4.0 * 2.0 * r_h * d_rms * 2.0 / (2 * h) + bound * np.abs(ref[inner]).max()
+            _report(f"cfg5 fd at {name} ({y},{x})", fd=fd, grad=float(got[y, x]), tol=float(tol))
+            assert abs(fd - got[y, x]) <= tol
+        I.grad = None
     k.free()

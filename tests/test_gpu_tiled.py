@@ -1,6 +1,6 @@
 """GPU parity of the binned (tiled) gridder against the FP64 oracle, through the C ABI.
 
-Covers fixed and per-plane supports, every precision, tile sizes 32/64/128 (results must
+Covers fixed and per-plane supports, every precision, tile sizes 16/32/64 (results must
 not depend on the tile), several images per call, and a hot tile that is split into
 several work items.
 """
