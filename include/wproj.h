@@ -173,6 +173,26 @@ int wproj_grid(const wproj_kernels *k, int64_t nvis, const double *uvw, const vo
                int64_t *counters, void *workspace, int64_t workspace_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): wproj_grid with its workspace taken
+ * from a fixed scratch array that the library holds in each GPU's memory
+ * (wproj_noalloc_scratch_bytes() = 256 MiB per GPU, from library load until the process
+ * ends) instead of from the caller.  Arguments, results, counters and errors are those
+ * of wproj_grid; nothing is allocated and no allocating library routine is called.
+ * A call whose wproj_workspace_size(k, nvis) exceeds the scratch size is refused with
+ * WPROJ_EWORKSPACE before anything is enqueued (roughly: a 2048^2 grid leaves room for
+ * a few million visibilities).  All calls on one GPU share that GPU's scratch array and
+ * the array keeps the last call's contents (each call clears what it relies on): calls
+ * that overlap in time on one GPU, from any stream or thread, race and must not be
+ * issued.
+ */
+int wproj_grid_noalloc(const wproj_kernels *k, int64_t nvis, const double *uvw, const void *vis,
+                       const void *weight, const int64_t *image_offsets, void *grid,
+                       double *weight_sum, int64_t *counters, void *stream);
+/* Bytes of the per-GPU scratch array behind wproj_grid_noalloc. */
+int64_t wproj_noalloc_scratch_bytes(void);
+
+/*
  * Degridding, the adjoint of gridding (prediction of model visibilities from a model
  * grid; the paper names gridding and degridding together as the steps earlier GPU and
  * Cell imagers accelerated, Section 2, and its imager's CLEAN cycles predict from the

@@ -22,10 +22,12 @@ from .wproj import (  # noqa: F401
     footprints,
     gather_rows,
     grid,
+    grid_noalloc,
     image,
     last_error,
     make_kernels,
     measure_lds,
+    noalloc_scratch_bytes,
     regroup_rows,
     version,
 )

@@ -24,7 +24,8 @@ EXPORTED = ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_w
             "wproj_profile", "wproj_profile_read", "wproj_last_error", "wproj_version",
             "wproj_footprints", "wproj_regroup_workspace_size", "wproj_regroup_rows",
             "wproj_gather_rows", "wproj_plan_create", "wproj_plan_free", "wproj_grid_planned",
-            "wproj_degrid_planned", "wproj_check_weights", "wproj_measure_lds")
+            "wproj_degrid_planned", "wproj_check_weights", "wproj_measure_lds",
+            "wproj_grid_noalloc", "wproj_noalloc_scratch_bytes")
 PHASES = ("bin", "grid", "plain", "fft", "correct", "degrid", "reduce")
 
 
@@ -92,12 +93,16 @@ def lib():
     L.wproj_regroup_rows.argtypes = [i64, vp, vp, ctypes.c_int32, vp, vp, vp, vp, i64, vp]
     L.wproj_gather_rows.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp]
     L.wproj_check_weights.argtypes = [vp, vp, vp]
+    L.wproj_grid_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.wproj_noalloc_scratch_bytes.argtypes = []
+    L.wproj_noalloc_scratch_bytes.restype = i64
     L.wproj_measure_lds.argtypes = [i32, ctypes.c_int32, vp, vp, vp]
     for name in ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_grid",
                  "wproj_degrid", "wproj_image", "wproj_autotune", "wproj_tuning", "wproj_profile",
                  "wproj_profile_read", "wproj_version", "wproj_footprints", "wproj_regroup_rows",
                  "wproj_gather_rows", "wproj_plan_create", "wproj_plan_free", "wproj_grid_planned",
-                 "wproj_degrid_planned", "wproj_check_weights", "wproj_measure_lds"):
+                 "wproj_degrid_planned", "wproj_check_weights", "wproj_measure_lds",
+                 "wproj_grid_noalloc"):
         getattr(L, name).restype = i32
     _lib = L
     return L

@@ -180,6 +180,28 @@ def measure_lds(mode: int, rounds: int = 4096, stream=None) -> tuple:
     return bps.value, ms.value
 
 
+def grid_noalloc(k: Kernels, uvw: torch.Tensor, vis: torch.Tensor, weight: torch.Tensor,
+                 grid_out: torch.Tensor, image_offsets: Optional[torch.Tensor] = None,
+                 weight_sum: Optional[torch.Tensor] = None, counters: Optional[torch.Tensor] = None,
+                 stream=None):
+    """wproj_grid_noalloc: wproj_grid with the library's fixed per-GPU scratch array as
+    workspace (nothing allocated; overlapping calls on one GPU race)."""
+    nvis = int(uvw.shape[0]) if uvw.dim() else 0
+    n, ni = k.params["n"], k.params.get("n_images", 1)
+    _lib.check("wproj_grid_noalloc", _lib.lib().wproj_grid_noalloc(
+        k.handle, nvis, _ptr(uvw, "uvw", torch.float64, 3 * nvis), _ptr(vis, "vis", k.cplx, nvis),
+        _ptr(weight, "weight", k.real, nvis),
+        _ptr(image_offsets, "image_offsets", torch.int64, ni + 1),
+        _ptr(grid_out, "grid", k.cplx, ni * n * n),
+        _ptr(weight_sum, "weight_sum", torch.float64, ni),
+        _ptr(counters, "counters", torch.int64, 3), _stream(stream)))
+
+
+def noalloc_scratch_bytes() -> int:
+    """wproj_noalloc_scratch_bytes: size of the per-GPU scratch array of grid_noalloc."""
+    return int(_lib.lib().wproj_noalloc_scratch_bytes())
+
+
 def autotune(k: Kernels, uvw: torch.Tensor, vis: torch.Tensor, weight: torch.Tensor,
              image_offsets: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
              stream=None) -> tuple:
