@@ -18,11 +18,11 @@ def lib():
             _build.build()
         L = ctypes.CDLL(_build.LIB)
         vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
-        L.wref_grid.argtypes = [i32, dbl, i32, dbl, i32, vp, i32, vp, vp, i64, vp, vp, vp, i32,
-                                vp, vp, vp, vp, i32]
+        L.wref_grid.argtypes = [i32, dbl, i32, dbl, i32, i32, vp, i32, vp, vp, i64, vp, vp, vp,
+                                i32, vp, vp, vp, vp, i32]
         L.wref_grid.restype = i32
-        L.wref_degrid.argtypes = [i32, dbl, i32, dbl, i32, vp, i32, vp, vp, i64, vp, i32, vp, vp,
-                                  vp, i32]
+        L.wref_degrid.argtypes = [i32, dbl, i32, dbl, i32, i32, vp, i32, vp, vp, i64, vp, i32, vp,
+                                  vp, vp, i32]
         L.wref_degrid.restype = i32
         _lib = L
     return _lib
@@ -45,12 +45,12 @@ def grid(plan: Plan, tables, uvw, vis, weight, image_offsets=None, nthreads: int
     uvw = np.ascontiguousarray(uvw, dtype=np.float64)
     vis = np.ascontiguousarray(vis, dtype=np.complex128)
     wt = np.ascontiguousarray(weight, dtype=np.float64)
-    G = out if out is not None else np.zeros((plan.n_images, plan.n, plan.n), dtype=np.complex128)
+    G = out if out is not None else np.zeros((plan.n_grids, plan.n, plan.n), dtype=np.complex128)
     sumw = np.zeros(plan.n_images)
     cnt = np.zeros(3, dtype=np.int64)
     io = None if image_offsets is None else np.ascontiguousarray(image_offsets, dtype=np.int64)
     rc = lib().wref_grid(plan.n, plan.cell, plan.n_w, plan.w_max, W_MODES.index(plan.w_mode),
-                         _p(supp), plan.O, _p(flat),
+                         plan.n_layers, _p(supp), plan.O, _p(flat),
                          _p(offs), uvw.shape[0], _p(uvw), _p(vis.view(np.float64)), _p(wt),
                          plan.n_images, None if io is None else _p(io), _p(G.view(np.float64)),
                          _p(sumw), _p(cnt), int(nthreads))
@@ -66,7 +66,7 @@ def degrid(plan: Plan, tables, uvw, M, image_offsets=None, nthreads: int = 1):
     out = np.zeros(uvw.shape[0], dtype=np.complex128)
     io = None if image_offsets is None else np.ascontiguousarray(image_offsets, dtype=np.int64)
     lib().wref_degrid(plan.n, plan.cell, plan.n_w, plan.w_max, W_MODES.index(plan.w_mode),
-                      _p(supp), plan.O, _p(flat),
+                      plan.n_layers, _p(supp), plan.O, _p(flat),
                       _p(offs), uvw.shape[0], _p(uvw), plan.n_images,
                       None if io is None else _p(io), _p(M.view(np.float64)),
                       _p(out.view(np.float64)), int(nthreads))

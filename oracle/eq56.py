@@ -55,3 +55,21 @@ def regroup_order(bidx, n_baselines: int):
         perm[fill[b[j]]] = j
         fill[b[j]] += 1
     return perm
+
+
+def channel_major_order(row_perm, bidx, n_baselines: int, n_chan: int):
+    """Visibility order after the regroup, channel by channel: the paper's CUDA gridder
+    walks one baseline's timestamps in sequence (Section 2.2); with n_chan channels per
+    row that is, for each baseline in turn and each channel c, the baseline's rows in
+    time order.  Visibility (row j, channel c) has source index j n_chan + c; returns the
+    source index of every position of that order."""
+    row_perm = np.asarray(row_perm, dtype=np.int64)
+    b = np.asarray(bidx, dtype=np.int64)
+    c = counts(b, n_baselines)
+    start = start_index(c)
+    out = []
+    for bl in range(n_baselines):
+        rows = row_perm[start[bl]:start[bl] + c[bl]]  # this baseline's rows, in time order
+        for ch in range(n_chan):
+            out.extend((rows * n_chan + ch).tolist())
+    return np.asarray(out, dtype=np.int64)

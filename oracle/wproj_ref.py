@@ -20,6 +20,17 @@ fixed explicitly:
       "fold_sqrt": w_p = w_max (p/(N_w - 1))^2, planes evenly spaced in sqrt|w|,
       plane = clamp(floor(sqrt(|w|/w_max) (N_w - 1) + 1/2)).  Degridding a folded row
       returns conj of the value degridded at (-u, -v, -w), the real-linear adjoint.
+      w-stacking hybrid (w_mode "stack", n_wlayers = L): the w range is cut into L layers
+      of width D = 2 w_max/L centred at w_l = -w_max + (l + 1/2) D, layer of w =
+      clamp(floor((w + w_max)/D)); each layer has its own grid, and a visibility is
+      gridded onto its layer's grid with the w-projection kernel of its residual
+      w - w_l, whose N_w planes are linear over [-D/2, D/2] (dw = D/(N_w - 1), plane =
+      clamp(floor((w - w_l + D/2)/dw + 1/2))).  Grids are [n_images L][N][N], layer
+      fastest.  The image sums the layers' centred inverse DFTs, each multiplied by
+      exp(+2 pi i w_l (n - 1)), n = sqrt(1 - l^2 - m^2) at the pixel (0 where
+      l^2 + m^2 >= 1), before the real part and the correction (O7); the adjoint
+      (O8) multiplies the corrected image by the conjugate factor before each layer's
+      forward DFT.  One layer is the linear layout exactly.
   O2  taper psi = normalised prolate spheroidal function, c = pi S/2 (pswf.py).
   O3  kernel table of plane p: the Fourier transform of psi(l) psi(m) times the
       w phase screen exp(+2 pi i w_p (sqrt(1-l^2-m^2) - 1)), sampled at m x m
@@ -51,7 +62,7 @@ import numpy as np
 from . import pswf
 
 PRECISIONS = ("f64", "f32", "f32_f16table")
-W_MODES = ("linear", "fold", "fold_sqrt")
+W_MODES = ("linear", "fold", "fold_sqrt", "stack")
 
 
 class Plan:
@@ -69,11 +80,20 @@ class Plan:
         self.m = int(params["kernel_image_size"])
         self.n_images = int(params.get("n_images", 1))
         wm = params.get("w_mode", "linear")
-        self.w_mode = W_MODES[wm] if isinstance(wm, (int, np.integer)) and 0 <= wm < 3 else wm
+        self.w_mode = W_MODES[wm] if isinstance(wm, (int, np.integer)) and 0 <= wm < 4 else wm
+        self.n_layers = int(params.get("n_wlayers", 1)) if self.w_mode == "stack" else 1
         self.validate()
         self.fov = float(self.n) * self.cell
-        self.fold = self.w_mode != "linear"
-        if self.n_w == 1:
+        self.fold = self.w_mode in ("fold", "fold_sqrt")
+        self.n_grids = self.n_images * self.n_layers
+        if self.w_mode == "stack":
+            self.layer_w = (2.0 * self.w_max) / float(self.n_layers)
+            self.w_layers = np.array([-self.w_max + (l + 0.5) * self.layer_w for l in range(self.n_layers)])
+            half = self.layer_w / 2.0
+            self.dw = self.layer_w / float(self.n_w - 1) if self.n_w > 1 else 0.0
+            self.w_planes = (np.array([-half + p * self.dw for p in range(self.n_w)]) if self.n_w > 1
+                             else np.zeros(1))
+        elif self.n_w == 1:
             self.dw = 0.0
             self.w_planes = np.zeros(1)
         elif self.w_mode == "linear":
@@ -101,6 +121,8 @@ class Plan:
             and 2 <= self.m <= 4096 and self.m % 2 == 0
             and self.n_images >= 1
             and self.w_mode in W_MODES
+            and 1 <= self.n_layers <= 4096
+            and (self.w_mode != "stack" or self.w_max > 0)
         )
         ok = ok and all(1 <= s <= 32 and s <= n and (s * O) % 2 == 0 for s in self.supports)
         if not ok:
@@ -120,11 +142,23 @@ def plane_index(plan: Plan, w: np.ndarray) -> np.ndarray:
         return np.zeros(w.shape, dtype=np.int64)
     if plan.w_mode == "linear":
         t = np.floor((w + plan.w_max) / plan.dw + 0.5)
+    elif plan.w_mode == "stack":  # w is the residual w - w_l
+        t = np.floor((w + plan.layer_w / 2.0) / plan.dw + 0.5)
     elif plan.w_mode == "fold":
         t = np.floor(w / plan.dw + 0.5)
     else:
         t = np.floor(np.sqrt(w / plan.w_max) * float(plan.n_w - 1) + 0.5)
     t = np.clip(np.nan_to_num(t, nan=0.0), 0, plan.n_w - 1)
+    return t.astype(np.int64)
+
+
+def layer_index(plan: Plan, w: np.ndarray) -> np.ndarray:
+    """w-stacking: the layer of w, floor((w + w_max)/D) clamped to [0, L - 1]."""
+    w = np.asarray(w, dtype=np.float64)
+    if plan.n_layers == 1:
+        return np.zeros(w.shape, dtype=np.int64)
+    t = np.floor((w + plan.w_max) / plan.layer_w)
+    t = np.clip(np.nan_to_num(t, nan=0.0), 0, plan.n_layers - 1)
     return t.astype(np.int64)
 
 
@@ -151,8 +185,9 @@ def snap(plan: Plan, uvw: np.ndarray, weight: np.ndarray):
     """Per-visibility geometry and validity.
 
     Returns dict with x0, y0, ou, ov, p (int64 arrays), valid (bool), fold (bool: the
-    row was mirrored to (-u, -v, -w) and its visibility is conjugated), and the
-    counters [dropped (non-finite uvw or off-grid), w clamped, bad weight].
+    row was mirrored to (-u, -v, -w) and its visibility is conjugated), layer (int64:
+    the w-stacking layer, 0 otherwise), and the counters [dropped (non-finite uvw or
+    off-grid), w clamped, bad weight].
     """
     uvw = np.asarray(uvw, dtype=np.float64)
     wt = np.asarray(weight, dtype=np.float64)
@@ -165,15 +200,24 @@ def snap(plan: Plan, uvw: np.ndarray, weight: np.ndarray):
     u = np.where(fin, uvw[:, 0] * sgn, 0.0)
     v = np.where(fin, uvw[:, 1] * sgn, 0.0)
     w = np.where(fin, uvw[:, 2] * sgn, 0.0)
+    if plan.w_mode == "stack":
+        layer = layer_index(plan, w)
+        w = w - (-plan.w_max + (layer + 0.5) * plan.layer_w)  # residual from the layer centre
+    else:
+        layer = np.zeros(w.shape, dtype=np.int64)
     p = plane_index(plan, w)
     supp = np.asarray(plan.supports, dtype=np.int64)[p]
     x0, ou, onx = axis_footprint(plan, u, supp)
     y0, ov, ony = axis_footprint(plan, v, supp)
     valid = consider & fin & onx & ony
     dropped = consider & ~valid
-    clamped = valid & (np.abs(uvw[:, 2]) > plan.w_max) if plan.n_w > 1 else np.zeros_like(valid)
+    if plan.n_w > 1 or plan.n_layers > 1:
+        clamped = valid & (np.abs(uvw[:, 2]) > plan.w_max)
+    else:
+        clamped = np.zeros_like(valid)
     counters = np.array([dropped.sum(), clamped.sum(), bad_w.sum()], dtype=np.int64)
-    return dict(x0=x0, y0=y0, ou=ou, ov=ov, p=p, valid=valid, fold=fold & valid, counters=counters)
+    return dict(x0=x0, y0=y0, ou=ou, ov=ov, p=p, valid=valid, fold=fold & valid, layer=layer,
+                counters=counters)
 
 
 def degrid_valid(plan: Plan, uvw: np.ndarray):
@@ -277,12 +321,13 @@ def _image_ranges(plan: Plan, nvis: int, image_offsets):
 
 
 def grid(plan: Plan, tables, uvw, vis, weight, image_offsets=None):
-    """O5: returns (grid complex128 [n_images][N][N], sumW [n_images], counters[3])."""
+    """O5: returns (grid complex128 [n_images L][N][N], sumW [n_images], counters[3]);
+    L = 1 except with w-stacking, where row j goes to grid img L + layer_j."""
     uvw = np.asarray(uvw, dtype=np.float64)
     vis = np.asarray(vis, dtype=np.complex128)
     weight = np.asarray(weight, dtype=np.float64)
     n = plan.n
-    G = np.zeros((plan.n_images, n, n), dtype=np.complex128)
+    G = np.zeros((plan.n_grids, n, n), dtype=np.complex128)
     sumw = np.zeros(plan.n_images)
     counters = np.zeros(3, dtype=np.int64)
     for img, (s, e) in enumerate(_image_ranges(plan, uvw.shape[0], image_offsets)):
@@ -297,10 +342,11 @@ def grid(plan: Plan, tables, uvw, vis, weight, image_offsets=None):
             S = T.shape[-1]
             x0, y0 = geo["x0"][sel], geo["y0"][sel]
             ou, ov = geo["ou"][sel], geo["ov"][sel]
+            gi = img * plan.n_layers + geo["layer"][sel]
             a = wv[sel]
             for kv in range(S):
                 for ku in range(S):
-                    np.add.at(G[img], (y0 + kv, x0 + ku), a * T[ov, ou, kv, ku])
+                    np.add.at(G, (gi, y0 + kv, x0 + ku), a * T[ov, ou, kv, ku])
     return G, sumw, counters
 
 
@@ -316,6 +362,8 @@ def grid_cells(plan: Plan, tables, uvw, vis, weight):
     summed per cell; for grids too large to hold densely on the host.
     Returns (cells int64 sorted, values complex128, sumW, counters[3]).
     """
+    if plan.n_layers != 1:
+        raise ValueError("grid_cells covers one grid per image (no w-stacking layers)")
     uvw = np.asarray(uvw, dtype=np.float64)
     geo = snap(plan, uvw, weight)
     vis = np.asarray(vis, dtype=np.complex128)
@@ -369,19 +417,47 @@ def centred_dft(img: np.ndarray) -> np.ndarray:
     return np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(img, axes=(-2, -1))), axes=(-2, -1))
 
 
+def layer_phase(plan: Plan, layer: int) -> np.ndarray:
+    """w-stacking: exp(+2 pi i w_l (sqrt(1 - l^2 - m^2) - 1)) at every pixel [y][x],
+    l = (x - N/2) cell, m = (y - N/2) cell; 0 where l^2 + m^2 >= 1."""
+    n = plan.n
+    lv = (np.arange(n) - n / 2.0) * plan.cell
+    r2 = lv[None, :] ** 2 + lv[:, None] ** 2
+    inside = r2 < 1.0
+    nterm = np.sqrt(np.where(inside, 1.0 - r2, 1.0)) - 1.0
+    return np.where(inside, np.exp(2j * np.pi * plan.w_layers[layer] * nterm), 0.0)
+
+
 def grid_to_image(plan: Plan, G: np.ndarray, sumw=None) -> np.ndarray:
-    """O6 + O7: real image kappa(x) kappa(y) Re(IDFT(G)) / sumW (sumW omitted if None)."""
+    """O6 + O7: real image kappa(x) kappa(y) Re(IDFT(G)) / sumW (sumW omitted if None).
+    With w-stacking, Re of the sum over layers of IDFT(G_l) times the layer's phase."""
     k = kappa(plan)
-    img = centred_idft(G).real * (k[None, :] * k[:, None])
+    if plan.w_mode == "stack":
+        L = plan.n_layers
+        G = np.asarray(G).reshape(-1, L, plan.n, plan.n)
+        acc = np.zeros((G.shape[0], plan.n, plan.n), dtype=np.complex128)
+        for l in range(L):
+            acc += centred_idft(G[:, l]) * layer_phase(plan, l)
+        img = acc.real * (k[None, :] * k[:, None])
+    else:
+        img = centred_idft(G).real * (k[None, :] * k[:, None])
     if sumw is not None:
         img = img / np.asarray(sumw, dtype=np.float64).reshape(-1, 1, 1)
     return img
 
 
 def image_to_grid(plan: Plan, img: np.ndarray) -> np.ndarray:
-    """O8: M = DFT(kappa kappa I), complex128, same leading shape as img."""
+    """O8: M = DFT(kappa kappa I), complex128, same leading shape as img.  With w-stacking,
+    layer l's grid is DFT(kappa kappa I conj(phase_l)): [n_images L][N][N]."""
     k = kappa(plan)
-    return centred_dft(np.asarray(img, dtype=np.float64) * (k[None, :] * k[:, None]))
+    corr = np.asarray(img, dtype=np.float64) * (k[None, :] * k[:, None])
+    if plan.w_mode != "stack":
+        return centred_dft(corr)
+    corr = corr.reshape(-1, plan.n, plan.n)
+    out = np.empty((corr.shape[0], plan.n_layers, plan.n, plan.n), dtype=np.complex128)
+    for l in range(plan.n_layers):
+        out[:, l] = centred_dft(corr * np.conj(layer_phase(plan, l)))
+    return out.reshape(-1, plan.n, plan.n)
 
 
 # ---------------------------------------------------------------------------
@@ -392,7 +468,7 @@ def image_to_grid(plan: Plan, img: np.ndarray) -> np.ndarray:
 def degrid(plan: Plan, tables, uvw, M, image_offsets=None):
     """V_j = sum_{kv,ku} conj(T_p[ov][ou][kv][ku]) M[y0+kv][x0+ku]; 0 for dropped rows."""
     uvw = np.asarray(uvw, dtype=np.float64)
-    M = np.asarray(M, dtype=np.complex128).reshape(plan.n_images, plan.n, plan.n)
+    M = np.asarray(M, dtype=np.complex128).reshape(plan.n_grids, plan.n, plan.n)
     out = np.zeros(uvw.shape[0], dtype=np.complex128)
     for img, (s, e) in enumerate(_image_ranges(plan, uvw.shape[0], image_offsets)):
         geo = degrid_valid(plan, uvw[s:e])
@@ -404,10 +480,11 @@ def degrid(plan: Plan, tables, uvw, M, image_offsets=None):
             S = T.shape[-1]
             x0, y0 = geo["x0"][sel], geo["y0"][sel]
             ou, ov = geo["ou"][sel], geo["ov"][sel]
+            gi = img * plan.n_layers + geo["layer"][sel]
             v = np.zeros(sel.sum(), dtype=np.complex128)
             for kv in range(S):
                 for ku in range(S):
-                    v += np.conj(T[ov, ou, kv, ku]) * M[img, y0 + kv, x0 + ku]
+                    v += np.conj(T[ov, ou, kv, ku]) * M[gi, y0 + kv, x0 + ku]
             acc[sel] = v
         # a folded row was degridded at (-u, -v, -w): its value is the conjugate
         out[s:e] = np.where(geo["fold"], np.conj(acc), acc)

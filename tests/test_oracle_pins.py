@@ -430,6 +430,23 @@ def test_eq6_scan_and_regroup_match_brute_force():
     assert (perm == np.argsort(b, kind="stable")).all()
 
 
+def test_channel_major_order_matches_lexicographic_sort():
+    """The channel-major visibility order is the sort of (baseline, channel, time) with
+    time the row's original position: checked against numpy's lexsort on a small case,
+    with empty baselines and an uneven row count per baseline."""
+    rng = np.random.default_rng(9)
+    n_b, n_chan = 12, 5
+    b = rng.integers(0, n_b, 300)
+    b[b == 3] = 4  # baseline 3 has no rows
+    perm = eq56.regroup_order(b, n_b)
+    got = eq56.channel_major_order(perm, b, n_b, n_chan)
+    rows = np.repeat(np.arange(len(b)), n_chan)
+    chans = np.tile(np.arange(n_chan), len(b))
+    want = np.lexsort((rows, chans, b[rows]))  # last key is the primary one
+    assert got.tolist() == want.tolist()
+    assert sorted(got.tolist()) == list(range(len(b) * n_chan))
+
+
 # --------------------------------------------------------------------------- sparse forms
 def test_sparse_grid_and_pixel_image_match_dense_forms():
     """grid_cells (the touched cells only, for grids too large for the host) holds exactly
@@ -596,3 +613,109 @@ def test_c_oracle_matches_numpy_oracle_folded(mode):
     M = np.random.default_rng(6).standard_normal((1, plan.n, plan.n)) + 1j
     assert np.abs(cref.degrid(plan, tabs, uvw, M, nthreads=4)
                   - R.degrid(plan, tabs, uvw, M)).max() < 1e-12 * np.abs(M).max()
+
+
+# --------------------------------------------------------------------------- w-stacking
+
+
+def _stack_plan(L, n_w=5, w_max=8.0, **kw):
+    base = dict(n=64, cell_rad=1e-3, n_wplanes=n_w, w_max=w_max, support=7, oversample=8,
+                kernel_image_size=32, w_mode="stack", n_wlayers=L)
+    base.update(kw)
+    return R.Plan(base)
+
+
+def test_stack_layer_worked_examples():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "stack_layers.txt"))
+            if l.strip() and not l.startswith("#")]
+    w = np.array([float(r[0]) for r in rows])
+    plan = _stack_plan(4)
+    assert plan.w_layers.tolist() == [-6.0, -2.0, 2.0, 6.0]
+    assert plan.w_planes.tolist() == [-2.0, -1.0, 0.0, 1.0, 2.0]
+    uvw = np.stack([np.full(len(w), 3.0), np.full(len(w), -2.0), w], axis=1)
+    g = R.snap(plan, uvw, np.ones(len(w)))
+    assert g["layer"].tolist() == [int(r[1]) for r in rows]
+    assert g["p"].tolist() == [int(r[2]) for r in rows]
+    assert g["counters"][1] == sum(int(r[3]) for r in rows)
+
+
+def test_stack_layer_and_plane_brute_force():
+    # nearest layer centre and nearest residual plane by enumeration (random w: no ties)
+    plan = _stack_plan(7, n_w=6, w_max=650.0)
+    w = np.random.default_rng(21).uniform(-640.0, 640.0, 4000)
+    lay = np.argmin(np.abs(w[:, None] - plan.w_layers[None, :]), axis=1)
+    res = w - plan.w_layers[lay]
+    pl = np.argmin(np.abs(res[:, None] - plan.w_planes[None, :]), axis=1)
+    g = R.snap(plan, np.stack([np.zeros_like(w), np.zeros_like(w), w], axis=1), np.ones(len(w)))
+    assert g["layer"].tolist() == lay.tolist()
+    assert g["p"].tolist() == pl.tolist()
+
+
+def test_stack_one_layer_is_the_linear_layout():
+    # one layer of width 2 w_max centred at 0 with N_w residual planes is the linear layout
+    # of N_w planes over [-w_max, w_max], operation for operation: identical grids
+    wl = synth.cfg1w(n_w=9, s_max=7)
+    base = {**wl.params, "support_per_plane": None, "support": 7}
+    lin = R.Plan({**base, "w_mode": "linear"})
+    st = R.Plan({**base, "w_mode": "stack", "n_wlayers": 1})
+    assert np.array_equal(lin.w_planes, st.w_planes)
+    G1, s1, c1 = R.grid(lin, R.kernel_tables(lin), wl.uvw, wl.vis, wl.weight)
+    G2, s2, c2 = R.grid(st, R.kernel_tables(st), wl.uvw, wl.vis, wl.weight)
+    assert np.array_equal(G1, G2) and np.array_equal(s1, s2) and c1.tolist() == c2.tolist()
+    assert np.array_equal(R.grid_to_image(lin, G1, s1), R.grid_to_image(st, G2, s2))
+
+
+def test_stack_direct_dft_falls_with_layers():
+    # the w-dominated tiny field (w FoV^2 up to ~4 cells), three residual planes per layer,
+    # support 7, oversampling 32: the error against the direct DFT with the w term falls
+    # as the layers multiply, to the level of 33-plane w-projection
+    wl = synth.cfg1w(n_w=33, oversample=32)
+    errs = []
+    for L in (1, 4, 16):
+        params = {**wl.params, "n_wplanes": 3, "w_mode": "stack", "n_wlayers": L,
+                  "support_per_plane": None, "support": 7}
+        sub = synth.Workload("s", params, wl.uvw, wl.vis, wl.weight)
+        plan, img = _wproj_image(sub)
+        geo = R.snap(plan, wl.uvw, wl.weight)
+        errs.append(_inner_err(img, _direct_dft_image(plan, wl.uvw, wl.vis, wl.weight, geo["valid"])))
+    print(f"stack: inner-half error vs the direct DFT for 1, 4, 16 layers: {errs}")
+    assert errs[1] < errs[0] / 2 and errs[2] < errs[1]
+    assert errs[2] < 6e-3
+
+
+def test_stack_adjoint_identity():
+    # imaging and prediction with layers: <Re sum_l IDFT(grid_l W x) phase_l kappa kappa, y>
+    # = Re <x, W A(y)>
+    wl = synth.cfg1w(n_w=17)
+    params = {**wl.params, "w_mode": "stack", "n_wlayers": 5, "n_wplanes": 4,
+              "support_per_plane": None, "support": 7}
+    plan = R.Plan(params)
+    tabs = R.kernel_tables(plan)
+    rng = np.random.default_rng(25)
+    x = rng.standard_normal(wl.nvis) + 1j * rng.standard_normal(wl.nvis)
+    W = rng.uniform(0.5, 2.0, wl.nvis)
+    y = rng.standard_normal((plan.n, plan.n))
+    img = R.grid_to_image(plan, R.grid(plan, tabs, wl.uvw, x, W)[0], None)[0]
+    back = W * R.predict(plan, tabs, wl.uvw, y)
+    lhs = np.sum(img * y)
+    rhs = np.real(np.vdot(x, back))
+    assert abs(lhs - rhs) < 1e-10 * np.linalg.norm(y) * np.linalg.norm(img)
+
+
+@pytest.mark.parametrize("nthreads", [1, 4])
+def test_c_oracle_matches_numpy_oracle_stacked(nthreads):
+    wl = synth.small_tracks(n=128, n_w=5, support=8, spp=None)
+    uvw = wl.uvw.numpy()
+    vis = wl.vis.numpy()
+    wt = np.random.default_rng(8).uniform(0.0, 2.0, wl.nvis)
+    offs = np.array([0, wl.nvis // 3, wl.nvis // 3, wl.nvis])
+    plan = R.Plan({**wl.params, "w_mode": "stack", "n_wlayers": 6, "n_images": 3})
+    tabs = R.kernel_tables(plan)
+    G, sw, cnt = R.grid(plan, tabs, uvw, vis, wt, offs)
+    assert G.shape[0] == 18 and len({int(i) for i in np.nonzero(np.abs(G).sum(axis=(1, 2)))[0]}) > 6
+    Gc, swc, cntc = cref.grid(plan, tabs, uvw, vis, wt, offs, nthreads=nthreads)
+    assert np.abs(Gc - G).max() <= 1e-12 * np.abs(G).max()
+    assert np.allclose(swc, sw, rtol=1e-13, atol=0) and cntc.tolist() == cnt.tolist()
+    M = np.random.default_rng(6).standard_normal((18, plan.n, plan.n)) + 1j
+    assert np.abs(cref.degrid(plan, tabs, uvw, M, offs, nthreads=nthreads)
+                  - R.degrid(plan, tabs, uvw, M, offs)).max() < 1e-12 * np.abs(M).max()
