@@ -63,7 +63,8 @@ def parse():
     ap.add_argument("--cpu-single-seconds", type=float, default=10.0,
                     help="work for the single-thread leg of the host oracle baseline")
     ap.add_argument("--no-extra-configs", action="store_true",
-                    help="skip timing the 4096^2 variable-support and 64-image workloads")
+                    help="skip timing the 4096^2 variable-support and 64-image workloads and "
+                         "the Hermitian-fold modes")
     ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the step replayed from a captured HIP graph")
     ap.add_argument("--tile", type=int, default=0, help="fix the tile side (skips autotuning)")
@@ -108,7 +109,10 @@ def main():
         sweep(args, dev)
         return
     lds_rates = measure_lds_peak()
-    peak_lds = max(lds_rates.values())
+    # the gridder's LDS traffic is a 64-bit read-add-write of each footprint cell: its
+    # roofline is the measured rate of exactly that access; reads alone run faster
+    peak_lds = lds_rates["read_add_write"]
+    peak_lds_read = lds_rates["read"]
     log(f"LDS rate (measured): { {k: round(v / 1e12, 2) for k, v in lds_rates.items()} } TB/s")
     t0 = time.time()
     wl = synth.cfg2(device=dev, precision="f32", hours=args.hours)
@@ -201,10 +205,11 @@ def main():
         "frac": achieved_lds / peak_lds,
         "traffic": (MEASURED_TRAFFIC["bytes"] if (tile, chunk) == (MEASURED_TRAFFIC["tile"],
                                                              MEASURED_TRAFFIC["chunk"]) else None),
-        "peak_source": "measured: wproj_measure_lds, best of 64-bit read / write / read-add-write",
+        "peak_source": "measured on the device: wproj_measure_lds, 64-bit read-add-write of the same word",
         "peak_measured_by_mode": {k: v / 1e9 for k, v in lds_rates.items()},
         "peak_spec": PEAK_LDS_SPEC / 1e9,
         "kernel_frac": achieved_lds / peak_lds,
+        "kernel_frac_vs_read_peak": achieved_lds / peak_lds_read,
         "kernel_frac_spec": achieved_lds / PEAK_LDS_SPEC,
         # the whole wproj_grid call (binning + tile gridder + partial-tile reduce)
         "call_ms": t_call * 1e3,
@@ -280,7 +285,13 @@ def main():
         torch.cuda.synchronize()
         gather_ms = ev0.elapsed_time(ev1) / reps
         gather_bytes = 2 * (uvw_rows.numel() * 8 + vis_rows.numel() * 8)
-        del uvw_out, vis_out, perm, a1, a2
+        del uvw_out, vis_out
+
+        # register accumulation over runs of a shared footprint origin (accumulate_runs),
+        # on the same visibilities put in baseline, channel, time order by the library
+        # (regroup by baseline, then the channel-major visibility permutation and gathers)
+        runs = run_accumulation(W, k, params, a1, a2, n_ant, n_ch, uvw, vis32, wt32, stream, reps)
+        del perm, a1, a2
 
     extra = {"phases_ms": per, "tuning": {"tile": tile, "chunk": chunk},
              "graph_replay_ms_per_step": graph_ms,
@@ -291,9 +302,10 @@ def main():
             "degrid": {"ms": degrid_ms, "bin_ms": degrid_bin_ms, "mvis_per_s": n_valid / degrid_ms / 1e3,
                        "kernel": "tiled_degrid_kernel",
                        "lds_read_bytes_per_vis": LDS_READ_BYTES_PER_VIS_DEGRID,
-                       "lds_frac": LDS_READ_BYTES_PER_VIS_DEGRID * n_valid / (degrid_ms * 1e-3) / peak_lds},
+                       "lds_frac": LDS_READ_BYTES_PER_VIS_DEGRID * n_valid / (degrid_ms * 1e-3) / peak_lds_read},
             "planned": {"grid_ms": planned_grid_ms, "grid_mvis_per_s": n_valid / planned_grid_ms / 1e3,
                         "degrid_ms": planned_degrid_ms},
+            "run_accumulation": runs,
             "regroup_by_baseline": {"rows": n_t * n_bl, "ms": regroup_ms, "gather_uvw_vis_ms": gather_ms,
                                     "gather_gb_per_s": gather_bytes / gather_ms / 1e6}})
     del ws
@@ -377,7 +389,7 @@ def main():
         del gh, wsh
         kh.free()
 
-    if not args.step_only:
+    if not args.step_only and not args.no_extra_configs:
         # Hermitian fold: rows with w < 0 gridded as conj(V) at (-u, -v, -w), 64 planes over
         # [0, w_max] (the plane spacing of the 128 linear planes, half the tables), evenly
         # spaced in w and in sqrt(w)
@@ -416,6 +428,42 @@ def main():
                 f"tables {tab_bytes / 1e6:.1f} MB")
             del gf, wsf
             kf.free()
+
+    if not args.step_only and not args.no_extra_configs:
+        # w-stacking hybrid: 16 layers of 9 residual planes (the grids, FFTs and the layer
+        # combination all grow with the layers)
+        ks = W.make_kernels({**params, "w_mode": "stack", "n_wlayers": 16, "n_wplanes": 9,
+                             "tile": 0, "chunk": 0})
+        gs = ks.new_grid()
+        wss = ks.workspace(nvis)
+        ts = W.autotune(ks, uvw, vis32, wt32, workspace=wss)
+        sws = torch.zeros(1, dtype=torch.float64, device=dev)
+
+        def step_s():
+            gs.zero_()
+            sws.zero_()
+            W.grid(ks, uvw, vis32, wt32, gs, weight_sum=sws, workspace=wss)
+            W.image(ks, W.GRID_TO_IMAGE, gs, img, sws, workspace=wss)
+
+        step_s()
+        torch.cuda.synchronize()
+        ks.profile(True)
+        ks.profile_read()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            step_s()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        mss = ev0.elapsed_time(ev1) / args.steps
+        phs = ks.profile_read()
+        ks.profile(False)
+        extra["stack"] = {"n_wlayers": 16, "n_wplanes": 9, "ms_per_step": mss,
+                          "mvis_per_s": n_valid / mss / 1e3,
+                          "phases_ms": {p: v / max(c, 1) for p, (v, c) in phs.items() if c},
+                          "tuning": {"tile": ts[0], "chunk": ts[1]}}
+        log(f"stack (16 layers x 9 planes): {mss:.3f} ms/step, {n_valid / mss / 1e3:.1f} Mvis/s")
+        del gs, wss
+        ks.free()
 
     if not args.step_only and not args.no_extra_configs:
         del wl, uvw, vis32, wt32, g, img
@@ -500,6 +548,71 @@ def sweep(args, dev):
                               "gridded": n_grid, "kernel_image_size": m}), flush=True)
             del ws, g
             k.free()
+
+
+def origin_runs(W, k, uvw, wt):
+    """Fraction of gridded visibilities whose footprint origin (x0, y0) and plane equal the
+    previous visibility's within a run the binning keeps together: consecutive
+    visibilities of one 64-visibility wavefront of the key pass with the same bin key take
+    consecutive slots of their bin, so the gridder meets them one after the other."""
+    import torch
+
+    t = k.tuning()[0]
+    fp = W.footprints(k, uvw, wt).long()
+    ok = fp[:, 5] == 0
+    key = ((fp[:, 1] // t) * 1_000_003 + fp[:, 0] // t) * 4099 + fp[:, 4]
+    same_run = torch.zeros_like(ok)
+    same_run[1:] = ok[1:] & ok[:-1] & (key[1:] == key[:-1])
+    idx = torch.arange(fp.shape[0], device=fp.device)
+    same_run &= (idx % 64) != 0
+    same = torch.zeros_like(ok)
+    same[1:] = same_run[1:] & (fp[1:, 0] == fp[:-1, 0]) & (fp[1:, 1] == fp[:-1, 1])
+    return float(same.sum().item()) / max(int(ok.sum().item()), 1)
+
+
+def run_accumulation(W, k, params, a1, a2, n_ant, n_ch, uvw, vis, wt, stream, reps):
+    """Gridding call (binning + tile gridder + reduce) with and without accumulate_runs, on
+    the measurement-set order and on the baseline/channel/time order, and the time of the
+    reorder itself."""
+    import torch
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    perm, start, counts = W.regroup_rows(a1, a2, n_ant)
+    vperm = W.regroup_channels(perm, start, counts, n_ant, n_ch)
+    uvw_c = W.gather_rows(vperm, uvw)
+    vis_c = W.gather_rows(vperm, vis)
+    wt_c = W.gather_rows(vperm, wt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    reorder_ms = e0.elapsed_time(e1)
+    del perm, start, counts, vperm
+    out = {"reorder_ms": reorder_ms,
+           "same_origin_fraction": {"ms_order": origin_runs(W, k, uvw, wt),
+                                    "channel_major": origin_runs(W, k, uvw_c, wt_c)}}
+    for order, (u, v, w) in (("ms_order", (uvw, vis, wt)), ("channel_major", (uvw_c, vis_c, wt_c))):
+        for mode in (False, True):
+            kr = W.make_kernels({**params, "tile": 0, "chunk": 0, "accumulate_runs": mode})
+            ws = kr.workspace(u.shape[0])
+            g = kr.new_grid()
+            tune = W.autotune(kr, u, v, w, workspace=ws)
+            W.grid(kr, u, v, w, g, workspace=ws)
+            torch.cuda.synchronize()
+            kr.profile(True)
+            kr.profile_read()
+            for _ in range(reps):
+                W.grid(kr, u, v, w, g, workspace=ws)
+            torch.cuda.synchronize()
+            ph = kr.profile_read()
+            kr.profile(False)
+            per = {p: a / max(c, 1) for p, (a, c) in ph.items() if c}
+            out[f"{order}_{'runs' if mode else 'plain'}"] = {
+                "grid_kernel_ms": per["grid"], "call_ms": per["bin"] + per["grid"] + per.get("reduce", 0.0),
+                "tuning": {"tile": tune[0], "chunk": tune[1]}}
+            del ws, g
+            kr.free()
+    log(f"run accumulation: {out}")
+    return out
 
 
 def measure_lds_peak():

@@ -8,6 +8,10 @@
  * the w phase screen, Fourier transformed), the grid is inverse-FFT'd and the
  * taper is divided out of the image.  Degridding is the adjoint.
  *
+ * Grids in WPROJ_W_STACK mode: a handle with L = n_wlayers layers has n_images L grids,
+ * [n_images][L][n][n]; every "grid" argument below is that array (images are still
+ * [n_images][n][n]).
+ *
  * Conventions shared by every entry point
  *   - Pointers are DEVICE pointers owned by the caller unless marked (host).
  *     Nothing returned by the library aliases caller memory.
@@ -54,8 +58,12 @@ typedef enum {
   WPROJ_W_LINEAR = 0,    /* N_w planes at w_p = -w_max + p 2 w_max/(N_w - 1) */
   WPROJ_W_FOLD = 1,      /* Hermitian fold: a row with w < 0 is gridded as conj(V) at
                             (-u, -v, -w); planes at w_p = p w_max/(N_w - 1) cover [0, w_max] */
-  WPROJ_W_FOLD_SQRT = 2  /* Hermitian fold with planes w_p = w_max (p/(N_w - 1))^2, evenly
+  WPROJ_W_FOLD_SQRT = 2, /* Hermitian fold with planes w_p = w_max (p/(N_w - 1))^2, evenly
                             spaced in sqrt(w); nearest plane in sqrt(|w|/w_max) (N_w - 1) */
+  WPROJ_W_STACK = 3      /* w-stacking hybrid: n_wlayers layers of width D = 2 w_max/n_wlayers
+                            centred at w_l = -w_max + (l + 1/2) D, layer = floor((w + w_max)/D)
+                            clamped; each layer has its own grid and a row is gridded with the
+                            kernel of its residual w - w_l, N_w planes linear over [-D/2, D/2] */
 } wproj_w_mode;
 
 typedef enum {
@@ -99,7 +107,20 @@ typedef struct {
                                with a real sky V(-u,-v,-w) = conj(V(u,v,w)), so Re of the image
                                is unchanged.  The paper's own imager uses planes over the full
                                w range (Section 3.1: 23 w-planes); the fold is a variant. */
-  int32_t reserved[3];      /* must be zero */
+  int32_t accumulate_runs;  /* 0 or 1.  1: while consecutive binned visibilities of a work item
+                               share a footprint origin, each lane of the gridder keeps its grid
+                               cell in a register and writes it to the LDS tile only when the
+                               origin changes (the paper's CUDA gridder buffers a baseline's
+                               successive timestamps in a register the same way, Section 2.2).
+                               Same arithmetic in the same order, so the grid is unchanged; it
+                               pays when visibilities come baseline by baseline, channel by
+                               channel, in time order (wproj_regroup_channels).  Used by the
+                               FP32 fixed-support (3..16) gridders, ignored elsewhere. */
+  int32_t n_wlayers;        /* WPROJ_W_STACK: layers L, 1..4096 (0 = 1); other modes: 0 or 1.
+                               Grids then hold n_images L planes [image][layer][n][n]; the
+                               image combines an image's layers (w-stacking, one of the
+                               wide-field methods the paper's introduction lists, Section 1). */
+  int32_t reserved[1];      /* must be zero */
 } wproj_params;
 
 typedef struct wproj_kernels wproj_kernels; /* opaque handle */
@@ -359,6 +380,23 @@ int64_t wproj_regroup_workspace_size(int64_t n_rows, int32_t n_ant);
 int wproj_regroup_rows(int64_t n_rows, const int32_t *ant1, const int32_t *ant2, int32_t n_ant,
                        int64_t *perm, int64_t *start, int64_t *counts, void *workspace,
                        int64_t workspace_bytes, void *stream);
+
+/*
+ * Visibility order for rows regrouped by baseline, channel by channel (the order in which
+ * the paper's CUDA gridder walks a baseline's samples, successive timestamps of one
+ * baseline and channel one after another, Section 2.2).  Inputs are the outputs of
+ * wproj_regroup_rows for n_rows rows of n_chan channels each (source visibility index
+ * row n_chan + c).  Baseline b's count_b rows become n_chan runs of count_b visibilities,
+ * one run per channel, each in time order:
+ *   vis_perm[start[b] n_chan + c counts[b] + t] = perm[start[b] + t] n_chan + c,
+ * t = 0 .. counts[b] - 1, c = 0 .. n_chan - 1.  vis_perm: int64 [n_rows n_chan] (device);
+ * apply it with wproj_gather_rows to per-visibility arrays (uvw rows of 24 bytes,
+ * visibilities, weights).  n_rows and n_ant as for wproj_regroup_rows; n_chan >= 1.
+ * Errors: WPROJ_EINVAL, WPROJ_EUNSUPPORTED, WPROJ_EHIP.
+ */
+int wproj_regroup_channels(int64_t n_rows, int32_t n_ant, int32_t n_chan, const int64_t *perm,
+                           const int64_t *start, const int64_t *counts, int64_t *vis_perm,
+                           void *stream);
 
 /*
  * Row gather, e.g. to apply a regroup permutation to the rows of uvw, visibilities or

@@ -28,6 +28,7 @@ from .wproj import (  # noqa: F401
     make_kernels,
     measure_lds,
     noalloc_scratch_bytes,
+    regroup_channels,
     regroup_rows,
     version,
 )

@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, "libwproj.so")
 
 F64, F32, F32_F16TABLE = 0, 1, 2
 ALGO_TILED, ALGO_PLAIN = 0, 1
-W_LINEAR, W_FOLD, W_FOLD_SQRT = 0, 1, 2
+W_LINEAR, W_FOLD, W_FOLD_SQRT, W_STACK = 0, 1, 2, 3
 GRID_TO_IMAGE, IMAGE_TO_GRID, GRID_TO_IMAGE_RAW = 0, 1, 2
 EXPORT_TABLES, EXPORT_TABLE_OFFSETS, EXPORT_KAPPA, EXPORT_TAPER, EXPORT_SUPPORTS = range(5)
 
@@ -24,8 +24,8 @@ EXPORTED = ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_w
             "wproj_profile", "wproj_profile_read", "wproj_last_error", "wproj_version",
             "wproj_footprints", "wproj_regroup_workspace_size", "wproj_regroup_rows",
             "wproj_gather_rows", "wproj_plan_create", "wproj_plan_free", "wproj_grid_planned",
-            "wproj_degrid_planned", "wproj_check_weights", "wproj_measure_lds",
-            "wproj_grid_noalloc", "wproj_noalloc_scratch_bytes")
+            "wproj_degrid_planned", "wproj_grid_noalloc", "wproj_noalloc_scratch_bytes",
+            "wproj_check_weights", "wproj_measure_lds", "wproj_regroup_channels")
 PHASES = ("bin", "grid", "plain", "fft", "correct", "degrid", "reduce")
 
 
@@ -45,7 +45,9 @@ class Params(ctypes.Structure):
         ("tile", ctypes.c_int32),
         ("chunk", ctypes.c_int32),
         ("w_mode", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("accumulate_runs", ctypes.c_int32),
+        ("n_wlayers", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 
@@ -92,17 +94,18 @@ def lib():
     L.wproj_regroup_workspace_size.restype = i64
     L.wproj_regroup_rows.argtypes = [i64, vp, vp, ctypes.c_int32, vp, vp, vp, vp, i64, vp]
     L.wproj_gather_rows.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp]
-    L.wproj_check_weights.argtypes = [vp, vp, vp]
     L.wproj_grid_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     L.wproj_noalloc_scratch_bytes.argtypes = []
     L.wproj_noalloc_scratch_bytes.restype = i64
+    L.wproj_check_weights.argtypes = [vp, vp, vp]
+    L.wproj_regroup_channels.argtypes = [i64, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp]
     L.wproj_measure_lds.argtypes = [i32, ctypes.c_int32, vp, vp, vp]
     for name in ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_grid",
                  "wproj_degrid", "wproj_image", "wproj_autotune", "wproj_tuning", "wproj_profile",
                  "wproj_profile_read", "wproj_version", "wproj_footprints", "wproj_regroup_rows",
                  "wproj_gather_rows", "wproj_plan_create", "wproj_plan_free", "wproj_grid_planned",
-                 "wproj_degrid_planned", "wproj_check_weights", "wproj_measure_lds",
-                 "wproj_grid_noalloc"):
+                 "wproj_degrid_planned", "wproj_grid_noalloc", "wproj_check_weights", "wproj_measure_lds",
+                 "wproj_regroup_channels"):
         getattr(L, name).restype = i32
     _lib = L
     return L

@@ -27,7 +27,7 @@ class WProjPredict(torch.autograd.Function):
         img = image.detach().to(k.real).reshape(ni, n, n).contiguous()
         nvis = uvw.shape[0]
         ws = k.workspace(nvis, device=image.device)
-        g = torch.empty((ni, n, n), dtype=k.cplx, device=image.device)
+        g = torch.empty((k.n_grids, n, n), dtype=k.cplx, device=image.device)
         W.image(k, W.IMAGE_TO_GRID, g, img, workspace=ws)
         out = torch.empty(nvis, dtype=k.cplx, device=image.device)
         W.degrid(k, uvw, g, out, image_offsets=image_offsets, workspace=ws)
@@ -48,7 +48,7 @@ class WProjPredict(torch.autograd.Function):
         g = grad_out.to(k.cplx).contiguous()
         ones = torch.ones(nvis, dtype=k.real, device=g.device)
         ws = k.workspace(nvis, device=g.device)
-        grid = torch.zeros((ni, n, n), dtype=k.cplx, device=g.device)
+        grid = torch.zeros((k.n_grids, n, n), dtype=k.cplx, device=g.device)
         W.grid(k, uvw, g, ones, grid, image_offsets=off, workspace=ws)
         img = torch.empty((ni, n, n), dtype=k.real, device=g.device)
         W.image(k, W.GRID_TO_IMAGE_RAW, grid, img, workspace=ws)

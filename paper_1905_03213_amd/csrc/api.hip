@@ -139,8 +139,16 @@ int validate(const wproj_params *p, std::vector<int32_t> &supp) {
     return fail(WPROJ_EINVAL, "tile must be 0, 16, 32 or 64");
   if (p->chunk != 0 && (p->chunk < 256 || p->chunk > 65536))
     return fail(WPROJ_EINVAL, "chunk must be 0 or in [256, 65536]");
-  if (p->w_mode < WPROJ_W_LINEAR || p->w_mode > WPROJ_W_FOLD_SQRT)
+  if (p->w_mode < WPROJ_W_LINEAR || p->w_mode > WPROJ_W_STACK)
     return fail(WPROJ_EINVAL, "unknown w_mode %d", p->w_mode);
+  if (p->w_mode == WPROJ_W_STACK) {
+    if (p->n_wlayers < 0 || p->n_wlayers > 4096) return fail(WPROJ_EINVAL, "n_wlayers must be in [0, 4096]");
+    if (!(p->w_max > 0.0)) return fail(WPROJ_EINVAL, "w-stacking needs w_max > 0");
+  } else if (p->n_wlayers != 0 && p->n_wlayers != 1) {
+    return fail(WPROJ_EINVAL, "n_wlayers > 1 needs w_mode WPROJ_W_STACK");
+  }
+  if (p->accumulate_runs != 0 && p->accumulate_runs != 1)
+    return fail(WPROJ_EINVAL, "accumulate_runs must be 0 or 1");
   for (int r : p->reserved)
     if (r != 0) return fail(WPROJ_EINVAL, "reserved fields must be zero");
   supp.assign(p->n_wplanes, p->support);
@@ -219,7 +227,7 @@ BinShape bin_shape(const wproj_kernels *k) {
   const int64_t n_sub = (int64_t)k->params.n_wplanes * k->params.oversample * k->params.oversample;
   B.pack_sub = k->uniform_support && k->s_max >= kMinFixedSupport && k->s_max <= kMaxFixedSupport &&
                n_sub <= (1ll << (32 - kLdsBits));
-  B.n_tiles = (int64_t)k->params.n_images * B.ntx * B.nty;
+  B.n_tiles = (int64_t)k->geo.n_grids * B.ntx * B.nty;
   B.n_keys = B.n_tiles * B.kw;
   return B;
 }
@@ -273,7 +281,7 @@ constexpr int kTuneChunks[] = {1024, 2048, 4096, 8192, 16384};
 
 bool plane_in_key_for(const wproj_kernels *k, int tile) {
   const int64_t nt = (k->params.n + tile - 1) / tile;
-  return (int64_t)k->params.n_images * nt * nt * k->params.n_wplanes <= (1ll << 25);
+  return (int64_t)k->geo.n_grids * nt * nt * k->params.n_wplanes <= (1ll << 25);
 }
 
 // Workspace for nvis visibilities under any tile/chunk the autotuner may select.
@@ -282,6 +290,7 @@ int64_t workspace_bytes_for(const wproj_kernels *k, int64_t nvis) {
   if (k->params.algorithm == WPROJ_ALGO_TILED) {
     wproj_kernels tmp;  // geometry only
     tmp.params = k->params;
+    tmp.geo = k->geo;
     tmp.s_max = k->s_max;
     tmp.uniform_support = k->uniform_support;
     for (int tile : kTuneTiles) {
@@ -299,12 +308,12 @@ int64_t workspace_bytes_for(const wproj_kernels *k, int64_t nvis) {
 }
 
 struct TuneKey {
-  int n, n_images, n_w, s_max, uniform, O, precision, w_mode;
+  int n, n_images, n_w, s_max, uniform, O, precision, w_mode, n_layers;
   int log2_nvis;
   bool operator<(const TuneKey &o) const {
-    return std::tie(n, n_images, n_w, s_max, uniform, O, precision, w_mode, log2_nvis) <
+    return std::tie(n, n_images, n_w, s_max, uniform, O, precision, w_mode, n_layers, log2_nvis) <
            std::tie(o.n, o.n_images, o.n_w, o.s_max, o.uniform, o.O, o.precision, o.w_mode,
-                    o.log2_nvis);
+                    o.n_layers, o.log2_nvis);
   }
 };
 std::mutex g_tune_mu;
@@ -411,7 +420,6 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
   } else {
     k->tile = 16;
   }
-  k->plane_in_key = plane_in_key_for(k, k->tile);
   if (params->chunk) k->chunk = params->chunk;
 
   Geometry &G = k->geo;
@@ -423,11 +431,17 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
   for (int b = 0; b < 9; ++b)
     if ((1 << b) == O) G.log2_O = b;
   G.w_mode = params->w_mode;
+  G.n_layers = G.w_mode == WPROJ_W_STACK && params->n_wlayers > 1 ? params->n_wlayers : 1;
+  G.n_grids = params->n_images * G.n_layers;
   G.fov = (double)n * params->cell_rad;
+  G.cell = params->cell_rad;
   G.w_max = params->w_max;
+  G.layer_w = G.w_mode == WPROJ_W_STACK ? (2.0 * params->w_max) / (double)G.n_layers : 0.0;
   G.dw = 0.0;
   if (n_w > 1 && G.w_mode == WPROJ_W_LINEAR) G.dw = (2.0 * params->w_max) / (double)(n_w - 1);
   if (n_w > 1 && G.w_mode == WPROJ_W_FOLD) G.dw = params->w_max / (double)(n_w - 1);
+  if (n_w > 1 && G.w_mode == WPROJ_W_STACK) G.dw = G.layer_w / (double)(n_w - 1);
+  k->plane_in_key = plane_in_key_for(k, k->tile);  // needs the number of grids
 
   if (hipMalloc(&k->d_supp, sizeof(int32_t) * n_w) != hipSuccess ||
       hipMalloc(&k->d_tab_off, sizeof(int64_t) * (n_w + 1)) != hipSuccess ||
@@ -459,8 +473,13 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
   HIP_TRY(hipMalloc(&tmp.p[3], (size_t)batch * so_max * so_max * 16));
   for (int p0 = 0; p0 < n_w; p0 += batch) {
     const int np = std::min(batch, n_w - p0);
-    HIP_TRY(launch_screen(k->d_taper, m, G.fov, G.w_max, G.dw, n_w, G.w_mode, p0, np,
-                          (double2 *)tmp.p[1], s));
+    // w-stacking tables are those of the residual planes, linear over [-D/2, D/2]
+    if (G.w_mode == WPROJ_W_STACK)
+      HIP_TRY(launch_screen(k->d_taper, m, G.fov, G.layer_w / 2.0, G.dw, n_w, WPROJ_W_LINEAR, p0, np,
+                            (double2 *)tmp.p[1], s));
+    else
+      HIP_TRY(launch_screen(k->d_taper, m, G.fov, G.w_max, G.dw, n_w, G.w_mode, p0, np,
+                            (double2 *)tmp.p[1], s));
     HIP_TRY(launch_table_dft((const double2 *)tmp.p[1], m, O, k->d_supp, p0, np, so_max,
                              (double2 *)tmp.p[2], (double2 *)tmp.p[3], s));
     HIP_TRY(launch_normalise((const double2 *)tmp.p[3], so_max, O, k->d_supp, k->d_tab_off, p0, np,
@@ -483,13 +502,14 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
   const size_t lengths[2] = {(size_t)n, (size_t)n};
   const rocfft_precision fp =
       params->precision == WPROJ_F64 ? rocfft_precision_double : rocfft_precision_single;
+  // one transform per grid: n_images of them, n_images x layers with w-stacking
   if (rocfft_plan_create(&k->fft_inv, rocfft_placement_inplace,
                          rocfft_transform_type_complex_inverse, fp, 2, lengths,
-                         (size_t)params->n_images, nullptr) != rocfft_status_success ||
+                         (size_t)G.n_grids, nullptr) != rocfft_status_success ||
       rocfft_plan_create(&k->fft_fwd, rocfft_placement_inplace,
                          rocfft_transform_type_complex_forward, fp, 2, lengths,
-                         (size_t)params->n_images, nullptr) != rocfft_status_success)
-    return fail(WPROJ_EFFT, "rocfft_plan_create failed for %dx%d x %d", n, n, params->n_images);
+                         (size_t)G.n_grids, nullptr) != rocfft_status_success)
+    return fail(WPROJ_EFFT, "rocfft_plan_create failed for %dx%d x %d", n, n, G.n_grids);
   size_t w1 = 0, w2 = 0;
   rocfft_plan_get_work_buffer_size(k->fft_inv, &w1);
   rocfft_plan_get_work_buffer_size(k->fft_fwd, &w2);
@@ -620,7 +640,7 @@ int wproj_autotune(wproj_kernels *k, int64_t nvis, const double *uvw, const void
   while (lg < 62 && (1ll << (lg + 1)) <= std::max<int64_t>(nvis, 1)) ++lg;
   const TuneKey key{k->params.n, k->params.n_images, k->params.n_wplanes, k->s_max,
                     k->uniform_support ? 1 : 0, k->params.oversample, k->params.precision,
-                    k->params.w_mode, lg};
+                    k->params.w_mode, k->geo.n_layers, lg};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -715,12 +735,13 @@ int wproj_degrid(const wproj_kernels *k, int64_t nvis, const double *uvw, const 
   if (k->n_taps > (int64_t)kTapMask)
     return fail(WPROJ_EUNSUPPORTED, "kernel tables of %lld taps exceed the tiled degridder's 2^26",
                 (long long)k->n_taps);
-  const BinShape B = bin_shape(k);
+  BinShape B = bin_shape(k);
   if (B.n_keys >= max_keys(k))
     return fail(WPROJ_EUNSUPPORTED, "%lld bins (images x tiles) exceed the tiled degridder's 32-bit keys",
                 (long long)B.n_keys);
   BinWorkspace W;
   carve(k, nvis, (char *)workspace, W);
+  B.pitch = degrid_pitch(k, B.tile);  // records binned for the degridder's own tile layout
   {
     PhaseTimer pt(k, WPROJ_PHASE_BIN, s);
     HIP_TRY(launch_bin(k, B, nvis, uvw, nullptr, nullptr, image_offsets, nullptr, nullptr, W, s));
@@ -935,6 +956,20 @@ int wproj_regroup_rows(int64_t n_rows, const int32_t *ant1, const int32_t *ant2,
                 (long long)need);
   HIP_TRY(launch_regroup(r, n_rows, ant1, ant2, n_ant, perm, start, counts, workspace,
                          (hipStream_t)stream));
+  return WPROJ_OK;
+}
+
+int wproj_regroup_channels(int64_t n_rows, int32_t n_ant, int32_t n_chan, const int64_t *perm,
+                           const int64_t *start, const int64_t *counts, int64_t *vis_perm, void *stream) {
+  g_err.clear();
+  const int rc = check_regroup_args(n_rows, n_ant);
+  if (rc != WPROJ_OK) return rc;
+  if (n_chan < 1) return fail(WPROJ_EINVAL, "n_chan must be >= 1");
+  if (n_rows > 0 && (!perm || !start || !counts || !vis_perm))
+    return fail(WPROJ_EINVAL, "perm, start, counts or vis_perm is NULL");
+  if (n_rows == 0) return WPROJ_OK;
+  const int64_t n_keys = (int64_t)n_ant * (n_ant + 1) / 2 + 1;
+  HIP_TRY(launch_channel_order(n_keys, n_chan, perm, start, counts, vis_perm, (hipStream_t)stream));
   return WPROJ_OK;
 }
 

@@ -55,10 +55,12 @@ __device__ inline uint32_t run_slot(uint32_t *count, uint32_t key) {
   return __shfl(got, leader, 64) + (uint32_t)(lane - leader);
 }
 
-// Bin key of a gridded visibility of image img.
-__device__ inline uint32_t bin_key(const BinShape &B, int img, const Footprint &f) {
+// Bin key of a gridded visibility of image img (of its grid: the image, or the image's
+// w-stacking layer).
+__device__ inline uint32_t bin_key(const Geometry &G, const BinShape &B, int img, const Footprint &f) {
   const uint32_t tx = (uint32_t)f.x0 >> B.log2_tile, ty = (uint32_t)f.y0 >> B.log2_tile;
-  const uint32_t tile = ((uint32_t)img * (uint32_t)B.nty + ty) * (uint32_t)B.ntx + tx;
+  const uint32_t g = (uint32_t)grid_of(G, img, f);
+  const uint32_t tile = (g * (uint32_t)B.nty + ty) * (uint32_t)B.ntx + tx;
   return B.kw > 1 ? tile * (uint32_t)B.kw + (uint32_t)f.p : tile;
 }
 
@@ -97,11 +99,11 @@ __global__ void __launch_bounds__(256)
       const Real wj = wt ? wt[j] : Real(1);
       cls = classify(G, uvw + 3 * j, wj, f);
       if (cls == kGridded) {
-        key = bin_key(B, img, f);
+        key = bin_key(G, B, img, f);
         fold = f.fold;
         if constexpr (COMPACT) packed = record_lds(G, B, f);
         w = (double)wj;
-        clamped = G.n_w > 1 && fabs(uvw[3 * j + 2]) > G.w_max;
+        clamped = w_clamped(G, uvw[3 * j + 2]);
       }
     }
   }
@@ -177,7 +179,8 @@ __global__ void __launch_bounds__(256)
     fold = (key & kFoldBit) != 0;
     key &= ~kFoldBit;
     r.lds = slots[2 * nvis + j];
-    r.tap = (r.lds >> kLdsBits) * (uint32_t)(S_fix * S_fix) | ((uint32_t)(S_fix - 1) << kTapBits);
+    if constexpr (kHasTap<Rec>)
+      r.tap = (r.lds >> kLdsBits) * (uint32_t)(S_fix * S_fix) | ((uint32_t)(S_fix - 1) << kTapBits);
   } else {
     const int img = image_of(img_off, G.n_images, j);
     if (img < 0) return;
@@ -186,11 +189,12 @@ __global__ void __launch_bounds__(256)
     const Real w = wt ? wt[j] : Real(1);
     if (classify(G, uvw + 3 * j, w, f) != kGridded) return;
     fold = f.fold;
-    key = bin_key(B, img, f);
+    key = bin_key(G, B, img, f);
     const int S = G.supp[f.p];
     r.lds = record_lds(G, B, f);
-    r.tap = (uint32_t)(G.tab_off[f.p] + (uint32_t)((f.ov * G.O + f.ou) * S * S)) |
-            ((uint32_t)(S - 1) << kTapBits);
+    if constexpr (kHasTap<Rec>)
+      r.tap = (uint32_t)(G.tab_off[f.p] + (uint32_t)((f.ov * G.O + f.ou) * S * S)) |
+              ((uint32_t)(S - 1) << kTapBits);
   }
   const Real w = wt ? wt[j] : Real(1);
   if (vis) {
@@ -198,7 +202,7 @@ __global__ void __launch_bounds__(256)
     const Cplx v = vis[j];
     r.wr = w * v.x;
     r.wi = (fold ? -w : w) * v.y;
-  } else {
+  } else if constexpr (kHasTap<Rec>) {
     // row-carrying records mark a folded row by a negative weight
     set_plan(r, fold ? -w : w, (uint32_t)j);
   }
@@ -440,7 +444,11 @@ hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, c
                          uvw, (const double2 *)vis, (const double *)wt, img_off, W.slots, W.offset, S_fix,
                          (RecordF64 *)W.rec);
   } else {
-    if (compact)
+    if (compact && vis)  // W V records of a fixed support: no tap word (12 bytes)
+      hipLaunchKernelGGL((scatter_kernel<float, float2, RecordF32P, true>), grid, block, 0, s, G, B, nvis,
+                         uvw, (const float2 *)vis, (const float *)wt, img_off, W.slots, W.offset, S_fix,
+                         (RecordF32P *)W.rec);
+    else if (compact)
       hipLaunchKernelGGL((scatter_kernel<float, float2, RecordF32, true>), grid, block, 0, s, G, B, nvis,
                          uvw, (const float2 *)vis, (const float *)wt, img_off, W.slots, W.offset, S_fix,
                          (RecordF32 *)W.rec);

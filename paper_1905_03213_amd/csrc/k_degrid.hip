@@ -9,7 +9,11 @@
 // Records go 8 at a time, a group of 8 lanes per record; lane r of a group takes
 // footprint rows kv = r, r + 8, ...: a row's S taps are contiguous in the sub-kernel and
 // its S cells contiguous in the LDS tile.  The group's partial sums are combined across
-// its 8 lanes and the first lane of the group stores V_j.
+// its 8 lanes and the first lane of the group stores V_j.  Binned for degridding alone,
+// the tile copy has an odd row pitch (degrid_pitch), so the rows of a footprint start on
+// different LDS banks whatever the bank count; plans share their records with the
+// gridder and keep its pitch (an odd multiple of 8 cells, which suits the gridder's
+// one-tap-per-lane pattern).
 #include <algorithm>
 
 #include "wproj_tiled.h"
@@ -251,7 +255,10 @@ hipError_t dispatch(const wproj_kernels *k, const BinShape &B, const TileShape &
 
 hipError_t launch_tiled_degrid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
                                const void *model_grid, void *vis_out, int64_t nvis, hipStream_t s) {
-  const TileShape ts = tile_shape(k, B.tile);
+  // the tile copy uses the row pitch the records' LDS offsets were binned with
+  TileShape ts = tile_shape(k, B.tile);
+  ts.pitch = B.pitch;
+  ts.lds_bytes = (size_t)ts.rows * ts.pitch * (k->params.precision == WPROJ_F64 ? 16 : 8);
   // rows that are dropped or belong to no image keep a zero prediction
   const int64_t words = nvis * (k->params.precision == WPROJ_F64 ? 4 : 2);
   hipError_t e = launch_fill_u32((uint32_t *)vis_out, words, 0u, s);

@@ -8,6 +8,8 @@
 // multiplies by the grid correction kappa(x) kappa(y) / sumW (the taper divided out of
 // the image).  Image -> grid runs the same identity backwards: one pass writes
 // (-1)^(kx+ky) kappa kappa I at the shifted position, then an in-place forward FFT.
+// With w-stacking an image has one grid per layer: the grid -> image pass combines the
+// layers' transforms with their phase factors, and image -> grid writes every layer.
 #include "wproj_internal.h"
 
 namespace wproj {
@@ -53,6 +55,90 @@ __global__ void i2g_kernel(int n, int n_images, const Real *__restrict__ img,
   G[2 * t + 1] = (Real)0;
 }
 
+// w-stacking: n - 1 at pixel (x, y), n = sqrt(1 - l^2 - m^2), l = (x - n/2) cell,
+// m = (y - n/2) cell; false outside the unit circle (no sky there: the layer factor is 0).
+__device__ inline bool n_minus_1(const Geometry &G, int x, int y, double &nm1) {
+#pragma clang fp contract(off)
+  const double l = ((double)x - (double)G.n / 2.0) * G.cell;
+  const double m = ((double)y - (double)G.n / 2.0) * G.cell;
+  const double r2 = l * l + m * m;
+  if (!(r2 < 1.0)) return false;
+  nm1 = sqrt(1.0 - r2) - 1.0;
+  return true;
+}
+
+// Layer centre w_l = -w_max + (l + 1/2) D, the same operations as the footprint rule.
+__device__ inline double layer_centre(const Geometry &G, int layer) {
+#pragma clang fp contract(off)
+  return -G.w_max + ((double)layer + 0.5) * G.layer_w;
+}
+
+// Grid -> image with w-stacking: for image i, Re(sum over layers l of
+// IDFT(G_{i,l})[y][x] exp(+2 pi i w_l (n - 1))) kappa(x) kappa(y) / sumW_i.  F holds the
+// unshifted inverse FFTs of the n_images L grids (layer fastest).
+template <typename Real>
+__global__ void g2i_stack_kernel(Geometry G, const Real *__restrict__ F,
+                                 const double *__restrict__ kappa, const double *__restrict__ wsum,
+                                 Real *__restrict__ img) {
+  const int n = G.n, L = G.n_layers;
+  const int64_t cells = (int64_t)n * n;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cells * G.n_images) return;
+  const int i = (int)(t / cells);
+  const int64_t r = t - (int64_t)i * cells;
+  const int y = (int)(r / n), x = (int)(r - (int64_t)y * n);
+  const int h = n / 2;
+  const int ys = y + h < n ? y + h : y - h;
+  const int xs = x + h < n ? x + h : x - h;
+  double nm1 = 0.0;
+  double acc = 0.0;
+  if (n_minus_1(G, x, y, nm1)) {
+    for (int l = 0; l < L; ++l) {
+      const int64_t e = 2 * (cells * ((int64_t)i * L + l) + (int64_t)ys * n + xs);
+      const double re = (double)F[e], im = (double)F[e + 1];
+      double sn, cs;
+      sincospi(2.0 * layer_centre(G, l) * nm1, &sn, &cs);
+      acc += re * cs - im * sn;  // Re((re + i im)(cs + i sn))
+    }
+  }
+  double scale = kappa[x] * kappa[y];
+  if (wsum != nullptr) {
+    const double s = wsum[i];
+    scale = s != 0.0 ? scale / s : 0.0;
+  }
+  const double v = ((x + y) & 1) ? -acc : acc;
+  img[t] = (Real)(v * scale);
+}
+
+// Image -> grids with w-stacking: layer l of image i gets the shifted, sign-flipped
+// kappa kappa I exp(-2 pi i w_l (n - 1)) (then forward FFTs, as for one grid).
+template <typename Real>
+__global__ void i2g_stack_kernel(Geometry G, const Real *__restrict__ img,
+                                 const double *__restrict__ kappa, Real *__restrict__ Gr) {
+  const int n = G.n, L = G.n_layers;
+  const int64_t cells = (int64_t)n * n;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cells * G.n_grids) return;
+  const int g = (int)(t / cells);
+  const int i = g / L, l = g - i * L;
+  const int64_t r = t - (int64_t)g * cells;
+  const int ky = (int)(r / n), kx = (int)(r - (int64_t)ky * n);
+  const int h = n / 2;
+  const int y = ky + h < n ? ky + h : ky - h;
+  const int x = kx + h < n ? kx + h : kx - h;
+  const double v = (double)img[cells * i + (int64_t)y * n + x] * (kappa[x] * kappa[y]);
+  double nm1 = 0.0, re = 0.0, im = 0.0;
+  if (n_minus_1(G, x, y, nm1)) {
+    double sn, cs;
+    sincospi(2.0 * layer_centre(G, l) * nm1, &sn, &cs);
+    re = v * cs;
+    im = -v * sn;
+  }
+  const bool odd = (kx + ky) & 1;
+  Gr[2 * t] = (Real)(odd ? -re : re);
+  Gr[2 * t + 1] = (Real)(odd ? -im : im);
+}
+
 }  // namespace
 
 hipError_t launch_g2i_correct(const wproj_kernels *k, const void *fgrid, void *image,
@@ -60,6 +146,15 @@ hipError_t launch_g2i_correct(const wproj_kernels *k, const void *fgrid, void *i
   const int n = k->params.n, ni = k->params.n_images;
   const int64_t total = (int64_t)n * n * ni;
   const unsigned blocks = (unsigned)((total + 255) / 256);
+  if (k->params.w_mode == WPROJ_W_STACK) {
+    if (k->params.precision == WPROJ_F64)
+      hipLaunchKernelGGL(g2i_stack_kernel<double>, dim3(blocks), dim3(256), 0, s, k->geo,
+                         (const double *)fgrid, k->d_kappa, wsum, (double *)image);
+    else
+      hipLaunchKernelGGL(g2i_stack_kernel<float>, dim3(blocks), dim3(256), 0, s, k->geo,
+                         (const float *)fgrid, k->d_kappa, wsum, (float *)image);
+    return hipGetLastError();
+  }
   if (k->params.precision == WPROJ_F64)
     hipLaunchKernelGGL(g2i_kernel<double>, dim3(blocks), dim3(256), 0, s, n, ni,
                        (const double *)fgrid, k->d_kappa, wsum, (double *)image);
@@ -72,6 +167,17 @@ hipError_t launch_g2i_correct(const wproj_kernels *k, const void *fgrid, void *i
 hipError_t launch_i2g_precorrect(const wproj_kernels *k, const void *image, void *grid,
                                  hipStream_t s) {
   const int n = k->params.n, ni = k->params.n_images;
+  if (k->params.w_mode == WPROJ_W_STACK) {
+    const int64_t total = (int64_t)n * n * k->geo.n_grids;
+    const unsigned blocks = (unsigned)((total + 255) / 256);
+    if (k->params.precision == WPROJ_F64)
+      hipLaunchKernelGGL(i2g_stack_kernel<double>, dim3(blocks), dim3(256), 0, s, k->geo,
+                         (const double *)image, k->d_kappa, (double *)grid);
+    else
+      hipLaunchKernelGGL(i2g_stack_kernel<float>, dim3(blocks), dim3(256), 0, s, k->geo,
+                         (const float *)image, k->d_kappa, (float *)grid);
+    return hipGetLastError();
+  }
   const int64_t total = (int64_t)n * n * ni;
   const unsigned blocks = (unsigned)((total + 255) / 256);
   if (k->params.precision == WPROJ_F64)

@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(256)
       c_bad += (c == kBadWeight);
       continue;
     }
-    if (G.n_w > 1 && fabs(uvw[3 * j + 2]) > G.w_max) ++c_clamp;
+    if (w_clamped(G, uvw[3 * j + 2])) ++c_clamp;
     if (img != wimg) {
       if (wimg >= 0 && wsum && lane == 0) unsafeAtomicAdd(&wsum[wimg], wacc);
       wacc = 0.0;
@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(256)
     const Real ar = w * v.x, ai = (f.fold ? -w : w) * v.y;  // a folded row enters conjugated
     const int S = G.supp[f.p];
     const Tab *T = tab + G.tab_off[f.p] + ((int64_t)f.ov * G.O + f.ou) * S * S;
-    Real *gimg = grid + 2 * cells * img;
+    Real *gimg = grid + 2 * cells * grid_of(G, img, f);
     for (int t = lane; t < S * S; t += 64) {
       const int kv = t / S, ku = t - kv * S;
       const auto k = load_tap(T, t);
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256)
         fold = f.fold;
         const int S = G.supp[f.p];
         const Tab *T = tab + G.tab_off[f.p] + ((int64_t)f.ov * G.O + f.ou) * S * S;
-        const Cplx *gimg = grid + cells * img;
+        const Cplx *gimg = grid + cells * grid_of(G, img, f);
         for (int kv = r; kv < S; kv += 8) {
           const Tab *trow = T + kv * S;
           const Cplx *grow = gimg + (int64_t)(f.y0 + kv) * G.n + f.x0;
@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(256)
   o[1] = on ? f.y0 : -1;
   o[2] = on ? f.ou : -1;
   o[3] = on ? f.ov : -1;
-  o[4] = on ? f.p : -1;
+  o[4] = on ? f.layer * G.n_w + f.p : -1;  // w-stacking: plane counted across layers
   o[5] = on && f.fold ? kGriddedFolded : cls;
 }
 

@@ -97,6 +97,39 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// Channel-major visibility order of regrouped rows: baseline b's count_b rows (starting
+// at start_b in the row permutation) become n_chan runs of count_b visibilities, one run
+// per channel, each in time order.  gridDim.y = baselines, gridDim.x blocks per baseline
+// stride over its count_b n_chan outputs (writes and perm reads both coalesced).
+__global__ void __launch_bounds__(256)
+    channel_order_kernel(int32_t n_chan, const int64_t *__restrict__ perm,
+                         const int64_t *__restrict__ start, const int64_t *__restrict__ counts,
+                         int64_t *__restrict__ vis_perm) {
+  const int64_t b = blockIdx.y;
+  const int64_t s0 = start[b], cnt = counts[b];
+  const int64_t total = cnt * n_chan;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = k / cnt, t = k - c * cnt;
+    vis_perm[s0 * n_chan + k] = perm[s0 + t] * n_chan + c;
+  }
+}
+
+// Small rows (at most 4 words): one thread per row.
+__global__ void __launch_bounds__(256)
+    gather_small_rows_kernel(int64_t n_rows, int words, const int64_t *__restrict__ perm,
+                             int64_t n_src_rows, const uint32_t *__restrict__ src,
+                             uint32_t *__restrict__ dst, unsigned long long *bad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_rows) return;
+  const int64_t p = perm[k];
+  if (p < 0 || p >= n_src_rows) {
+    if (bad) atomicAdd(bad, 1ull);
+    return;
+  }
+  for (int i = 0; i < words; ++i) dst[k * words + i] = src[p * words + i];
+}
+
 // dst row k <- src row perm[k], rows of `words` elements of type V (4 or 16 bytes); each
 // wavefront copies one row at a time.
 template <typename V>
@@ -162,12 +195,27 @@ hipError_t launch_regroup(const RegroupShape &r, int64_t n_rows, const int32_t *
   return hipGetLastError();
 }
 
+hipError_t launch_channel_order(int64_t n_keys, int32_t n_chan, const int64_t *perm,
+                                const int64_t *start, const int64_t *counts, int64_t *vis_perm,
+                                hipStream_t s) {
+  if (n_keys == 0) return hipSuccess;
+  hipLaunchKernelGGL(channel_order_kernel, dim3(16, (unsigned)n_keys), dim3(256), 0, s, n_chan, perm,
+                     start, counts, vis_perm);
+  return hipGetLastError();
+}
+
 hipError_t launch_gather_rows(int64_t n_rows, int64_t row_bytes, const int64_t *perm,
                               int64_t n_src_rows, const void *src, void *dst, int64_t *bad,
                               hipStream_t s) {
   if (n_rows == 0) return hipSuccess;
-  const unsigned blocks = (unsigned)std::min<int64_t>((n_rows + 3) / 4, 1 << 16);
   auto *b = reinterpret_cast<unsigned long long *>(bad);
+  if (row_bytes <= 16) {
+    hipLaunchKernelGGL(gather_small_rows_kernel, dim3((unsigned)((n_rows + 255) / 256)), dim3(256), 0, s,
+                       n_rows, (int)(row_bytes / 4), perm, n_src_rows, (const uint32_t *)src,
+                       (uint32_t *)dst, b);
+    return hipGetLastError();
+  }
+  const unsigned blocks = (unsigned)std::min<int64_t>((n_rows + 3) / 4, 1 << 16);
   // 16-byte moves when rows and both buffers allow them
   if (row_bytes % 16 == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0 &&
       (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {

@@ -144,8 +144,12 @@ __device__ inline void accumulate(C2 *acc, int a, Real wr, Real wi, const Tap &t
 }
 
 // S = fixed support (0 = per-record support).  PLANNED: the records are row-carrying
-// (weight, row) and W V is formed from vis[row] as each record is loaded.
-template <typename Real, typename Rec, typename Tab, int S, bool PLANNED>
+// (weight, row) and W V is formed from vis[row] as each record is loaded.  RUNS (paired
+// fixed-support path only): while consecutive records of the work item share the
+// footprint origin, each lane keeps its cell of the footprint in a register and writes it
+// back to the tile only when the origin changes.  The multiply-adds and their order are
+// those of the plain read-add-write, so the result is the same bit for bit.
+template <typename Real, typename Rec, typename Tab, int S, bool PLANNED, bool RUNS = false>
 __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
     tiled_grid_kernel(Geometry G, BinShape B, int pitch, int rows, int wave_lds,
                       const Tab *__restrict__ tab, uint32_t tab_bytes,
@@ -183,7 +187,7 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         if constexpr (PLANNED) to_weighted(dst, vis);
       } else {  // padding records carry zero weight
         dst.lds = 0;
-        dst.tap = 0;
+        if constexpr (kHasTap<Rec>) dst.tap = 0;
         dst.wr = Real(0);
         dst.wi = Real(0);
       }
@@ -238,6 +242,28 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         const uint32_t d = (bcast(batch.lds, j + 1) >> kLdsBits) * kSubBytes - a;
         return P::load(tab_rsrc, a + (upper & d) + p_pair[q]);
       };
+      // RUNS: the lane's cells of the current origin (one per pass) and that origin's LDS
+      // offset (wave-uniform; -1 before the first record)
+      float2 held[kPasses];
+      int held_base = -1;
+      auto run_record = [&](int base, Real wr, Real wi, const float2 (&t)[kPasses]) {
+        if (base != held_base) {  // a new origin: write the held cells back, load the new ones
+#pragma unroll
+          for (int q = 0; q < kPasses; ++q)
+            if (held_base >= 0 && p_on[q]) acc[held_base + p_off[q]] = held[q];
+#pragma unroll
+          for (int q = 0; q < kPasses; ++q)
+            if (p_on[q]) held[q] = acc[base + p_off[q]];
+          held_base = base;
+        }
+#pragma unroll
+        for (int q = 0; q < kPasses; ++q) {
+          held[q].x = fmadd(wr, t[q].x, held[q].x);
+          held[q].x = fmadd(-wi, t[q].y, held[q].x);
+          held[q].y = fmadd(wr, t[q].y, held[q].y);
+          held[q].y = fmadd(wi, t[q].x, held[q].y);
+        }
+      };
       Rec cur;
       load_batch(0, cur);
       for (uint32_t b = 0; b < n_rec; b += 64) {
@@ -265,18 +291,31 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
             const int base1 = (int)(bcast(cur.lds, j + 1) & kLdsMask);
             const Real wr0 = bcast(cur.wr, j), wi0 = bcast(cur.wi, j);
             const Real wr1 = bcast(cur.wr, j + 1), wi1 = bcast(cur.wi, j + 1);
+            if constexpr (RUNS) {
+              float2 t0[kPasses], t1[kPasses];
 #pragma unroll
-            for (int q = 0; q < kPasses; ++q) {
-              float2 t0, t1;
-              P::split(c[gI & 1][i][q], t0, t1);
-              if (p_on[q]) {
-                accumulate(acc, base0 + p_off[q], wr0, wi0, t0);
-                accumulate(acc, base1 + p_off[q], wr1, wi1, t1);
+              for (int q = 0; q < kPasses; ++q) P::split(c[gI & 1][i][q], t0[q], t1[q]);
+              run_record(base0, wr0, wi0, t0);
+              run_record(base1, wr1, wi1, t1);
+            } else {
+#pragma unroll
+              for (int q = 0; q < kPasses; ++q) {
+                float2 t0, t1;
+                P::split(c[gI & 1][i][q], t0, t1);
+                if (p_on[q]) {
+                  accumulate(acc, base0 + p_off[q], wr0, wi0, t0);
+                  accumulate(acc, base1 + p_off[q], wr1, wi1, t1);
+                }
               }
             }
           }
         }
         if (more) cur = nxt;
+      }
+      if constexpr (RUNS) {
+#pragma unroll
+        for (int q = 0; q < kPasses; ++q)
+          if (held_base >= 0 && p_on[q]) acc[held_base + p_off[q]] = held[q];
       }
     } else if constexpr (S > 0) {
       // Direct-fetch path (fixed support, FP64): lane t handles tap t of every record, in
@@ -333,7 +372,7 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         }
         if (more) cur = nxt;
       }
-    } else {
+    } else if constexpr (kHasTap<Rec>) {
       // General path (per-record support up to 32): records by wave-uniform loads, each
       // record's taps in passes of 64 lanes.
       for (uint32_t r = w.begin; r < w.end; ++r) {
@@ -371,7 +410,7 @@ __global__ void __launch_bounds__(256)
                        const uint32_t *__restrict__ choff, Real *grid) {
   const int64_t cells = (int64_t)G.n * G.n;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cells * G.n_images) return;
+  if (t >= cells * G.n_grids) return;
   const int img = (int)(t / cells);
   const int64_t c = t - (int64_t)img * cells;
   const int Y = (int)(c / G.n), X = (int)(c - (int64_t)Y * G.n);
@@ -397,10 +436,10 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-template <typename Real, typename Rec, typename Tab, int S, bool PLANNED>
+template <typename Real, typename Rec, typename Tab, int S, bool PLANNED, bool RUNS = false>
 hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
                       const BinWorkspace &W, void *grid, const void *vis, hipStream_t s) {
-  auto kern = tiled_grid_kernel<Real, Rec, Tab, S, PLANNED>;
+  auto kern = tiled_grid_kernel<Real, Rec, Tab, S, PLANNED, RUNS>;
   // as many wavefronts per workgroup (up to 4) as their private tiles fit in LDS
   const int wpb = (int)std::max<size_t>(1, std::min<size_t>(kMaxWavesPerBlock, k->max_lds / ts.lds_bytes));
   const size_t lds = ts.lds_bytes * wpb;
@@ -429,7 +468,7 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
 template <typename Real>
 hipError_t launch_reduce(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
                          const BinWorkspace &W, void *grid, hipStream_t s) {
-  const int64_t total = (int64_t)k->params.n * k->params.n * k->params.n_images;
+  const int64_t total = (int64_t)k->params.n * k->params.n * k->geo.n_grids;
   hipLaunchKernelGGL(tile_reduce_kernel<Real>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
                      s, k->geo, B, ts.rows, (const typename Cx<Real>::T *)W.partial, W.choff,
                      (Real *)grid);
@@ -440,9 +479,15 @@ template <typename Real, typename Rec, typename Tab, bool PLANNED, int S>
 hipError_t dispatch_fixed(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
                           const BinWorkspace &W, void *grid, const void *vis, hipStream_t s) {
   if constexpr (S > kMaxFixedSupport) {
-    return launch_one<Real, Rec, Tab, 0, PLANNED>(k, B, ts, W, grid, vis, s);
+    if constexpr (!kHasTap<Rec>) return hipErrorInvalidValue;  // packed records need a fixed support
+    else return launch_one<Real, Rec, Tab, 0, PLANNED>(k, B, ts, W, grid, vis, s);
   } else {
-    if (k->s_max == S) return launch_one<Real, Rec, Tab, S, PLANNED>(k, B, ts, W, grid, vis, s);
+    if (k->s_max == S) {
+      if constexpr (kPairedTab<Tab>)
+        if (k->params.accumulate_runs)
+          return launch_one<Real, Rec, Tab, S, PLANNED, true>(k, B, ts, W, grid, vis, s);
+      return launch_one<Real, Rec, Tab, S, PLANNED>(k, B, ts, W, grid, vis, s);
+    }
     return dispatch_fixed<Real, Rec, Tab, PLANNED, S + 1>(k, B, ts, W, grid, vis, s);
   }
 }
@@ -461,8 +506,12 @@ hipError_t dispatch_support(const wproj_kernels *k, const BinShape &B, const Til
 template <typename Real, typename Rec, typename Tab>
 hipError_t dispatch_planned(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
                             const BinWorkspace &W, void *grid, const void *vis, hipStream_t s) {
-  return vis ? dispatch_support<Real, Rec, Tab, true>(k, B, ts, W, grid, vis, s)
-             : dispatch_support<Real, Rec, Tab, false>(k, B, ts, W, grid, vis, s);
+  if (vis) return dispatch_support<Real, Rec, Tab, true>(k, B, ts, W, grid, vis, s);
+  // FP32 W V records of a fixed support are the 12-byte packed form
+  if constexpr (std::is_same_v<Rec, RecordF32>)
+    if (B.pack_sub)
+      return dispatch_fixed<Real, RecordF32P, Tab, false, kMinFixedSupport>(k, B, ts, W, grid, vis, s);
+  return dispatch_support<Real, Rec, Tab, false>(k, B, ts, W, grid, vis, s);
 }
 
 // Fills the pair-ordered table: one thread per entry.  In pass q of a sub-kernel (n_q
@@ -522,6 +571,8 @@ TileShape tile_shape(const wproj_kernels *k, int tile) {
   t.lds_bytes = 2 * (size_t)t.rows * t.pitch * real;  // per wavefront
   return t;
 }
+
+int degrid_pitch(const wproj_kernels *k, int tile) { return (tile + k->s_max - 1) | 1; }
 
 hipError_t launch_tiled_grid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
                              void *grid, hipStream_t s, const void *vis) {

@@ -26,11 +26,16 @@ struct Geometry {
   int32_t n_w;      // w-planes
   int32_t n_images;
   int32_t log2_O;   // log2(O) when O is a power of two, else -1
-  int32_t w_mode;   // wproj_w_mode: linear over [-w_max, w_max], or a Hermitian fold
+  int32_t w_mode;   // wproj_w_mode: linear over [-w_max, w_max], a Hermitian fold, or stacking
+  int32_t n_layers; // w-stacking layers L (1 otherwise)
+  int32_t n_grids;  // n_images * n_layers
   double fov;       // n * cell_rad
   double w_max;
   double dw;        // plane spacing: 2 w_max / (n_w - 1) (linear), w_max / (n_w - 1) (fold),
-                    // 0 for a single plane or the square-root spacing
+                    // layer_w / (n_w - 1) (stacking: residual planes), 0 for a single plane
+                    // or the square-root spacing
+  double layer_w;   // w-stacking layer width 2 w_max / L (0 otherwise)
+  double cell;      // cell_rad (image-plane phase of the stacking layers)
   const int32_t *supp;     // device [n_w] full support per plane
   const int64_t *tab_off;  // device [n_w + 1] first tap of each plane
 };
@@ -42,6 +47,7 @@ constexpr int kGriddedFolded = 4;
 struct Footprint {
   int x0, y0, ou, ov, p;
   bool fold;  // taken at (-u, -v, -w): the visibility enters conjugated
+  int layer;  // w-stacking layer (0 otherwise); the row's grid is img * n_layers + layer
 };
 
 // floor(a / b) for b > 0
@@ -60,6 +66,8 @@ __device__ inline int plane_of(const Geometry &G, double w) {
   double t;
   if (G.w_mode == WPROJ_W_LINEAR)
     t = floor((w + G.w_max) / G.dw + 0.5);
+  else if (G.w_mode == WPROJ_W_STACK)  // w is the residual from the layer centre
+    t = floor((w + G.layer_w / 2.0) / G.dw + 0.5);
   else if (G.w_mode == WPROJ_W_FOLD)
     t = floor(w / G.dw + 0.5);
   else
@@ -67,6 +75,17 @@ __device__ inline int plane_of(const Geometry &G, double w) {
   if (!(t >= 0.0)) return 0;
   if (t > (double)(G.n_w - 1)) return G.n_w - 1;
   return (int)t;
+}
+
+// w-stacking: the layer of w, floor((w + w_max) / D) clamped to [0, L - 1], and w's
+// residual from that layer's centre -w_max + (layer + 1/2) D, each step rounded in FP64.
+__device__ inline int layer_residual(const Geometry &G, double &w) {
+#pragma clang fp contract(off)
+  double t = floor((w + G.w_max) / G.layer_w);
+  int layer = 0;
+  if (t >= 0.0) layer = t > (double)(G.n_layers - 1) ? G.n_layers - 1 : (int)t;
+  w = w - (-G.w_max + ((double)layer + 0.5) * G.layer_w);
+  return layer;
 }
 
 // One axis of the footprint: g = coord FoV + n/2 cells, q = floor(g O + 1/2) on the
@@ -102,17 +121,29 @@ __device__ inline int classify(const Geometry &G, const double *uvw, WT wt, Foot
   if (!(isfinite(u) && isfinite(v) && isfinite(w))) return kDropped;
   // Hermitian fold: V(-u, -v, -w) = conj(V(u, v, w)) for a real sky, so a row with w < 0
   // is gridded as conj(V) at the mirrored point and the planes only cover w >= 0
-  f.fold = G.w_mode != WPROJ_W_LINEAR && w < 0.0;
+  f.fold = (G.w_mode == WPROJ_W_FOLD || G.w_mode == WPROJ_W_FOLD_SQRT) && w < 0.0;
   if (f.fold) {
     u = -u;
     v = -v;
     w = -w;
   }
+  f.layer = G.w_mode == WPROJ_W_STACK ? layer_residual(G, w) : 0;
   f.p = plane_of(G, w);
   const int S = G.supp[f.p];
   if (!axis_footprint(G, u, S, f.x0, f.ou)) return kDropped;
   if (!axis_footprint(G, v, S, f.y0, f.ov)) return kDropped;
   return kGridded;
+}
+
+// Grid of a gridded row of image img: one grid per image, or per (image, layer) when
+// w-stacking.
+__device__ inline int grid_of(const Geometry &G, int img, const Footprint &f) {
+  return img * G.n_layers + f.layer;
+}
+
+// |w| beyond w_max is clamped to the edge plane (or layer) and counted.
+__device__ inline bool w_clamped(const Geometry &G, double w) {
+  return (G.n_w > 1 || G.n_layers > 1) && fabs(w) > G.w_max;
 }
 
 // Image owning row j: the largest i with off[i] <= j, or -1 outside [off[0], off[n_images]).

@@ -1,6 +1,8 @@
 // Shapes and buffers of the binned (tiled) gridding path.
 #pragma once
 
+#include <type_traits>
+
 #include "wproj_internal.h"
 
 namespace wproj {
@@ -40,6 +42,13 @@ struct RecordF64 {
   uint32_t tap;
   double wr, wi;
 };
+// The FP32 W V record of a fixed support whose sub-kernel number rides in `lds` (packed
+// records): the first tap is that number times S^2, so no tap word is stored (12 bytes).
+struct RecordF32P {
+  uint32_t lds;
+  float wr, wi;
+};
+template <typename Rec> constexpr bool kHasTap = !std::is_same_v<Rec, RecordF32P>;
 
 // Row-carrying records (degridding and planned gridding) hold the visibility's weight in
 // `wr` and its row in the low 32 bits of `wi` instead of W V.
@@ -86,7 +95,7 @@ struct WorkItem {
 // Workspace carve-up for one call (all device pointers).
 struct BinWorkspace {
   uint32_t *slots;     // [nvis]; [3 nvis] (slot, key, record word) when pack_sub
-  void *rec;           // [nvis] RecordF32 / RecordF64
+  void *rec;           // [nvis] RecordF32 / RecordF32P / RecordF64
   uint32_t *count;     // [n_keys]
   uint32_t *offset;    // [n_keys + 1]
   uint32_t *nch;       // [n_tiles]
@@ -121,6 +130,9 @@ struct TileShape {
   size_t lds_bytes;
 };
 TileShape tile_shape(const wproj_kernels *k, int tile);
+// Row pitch (complex cells) of the degridder's tile copy when records are binned for
+// degridding only: the smallest odd pitch >= T + S_max - 1.
+int degrid_pitch(const wproj_kernels *k, int tile);
 // Entries per sub-kernel of the pair-ordered table for support S, and the launch that
 // fills k->d_tab_pair from k->d_tab.
 int64_t pair_table_stride(int S);
@@ -148,6 +160,9 @@ int64_t regroup_workspace_bytes(const RegroupShape &r);
 hipError_t launch_regroup(const RegroupShape &r, int64_t n_rows, const int32_t *ant1,
                           const int32_t *ant2, int32_t n_ant, int64_t *perm, int64_t *start,
                           int64_t *counts, void *workspace, hipStream_t s);
+hipError_t launch_channel_order(int64_t n_keys, int32_t n_chan, const int64_t *perm,
+                                const int64_t *start, const int64_t *counts, int64_t *vis_perm,
+                                hipStream_t s);
 hipError_t launch_gather_rows(int64_t n_rows, int64_t row_bytes, const int64_t *perm,
                               int64_t n_src_rows, const void *src, void *dst, int64_t *bad,
                               hipStream_t s);

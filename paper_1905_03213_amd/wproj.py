@@ -18,7 +18,8 @@ from ._lib import (ALGO_PLAIN, ALGO_TILED, F32, F32_F16TABLE, F64, GRID_TO_IMAGE
 
 _PREC = {"f64": F64, "f32": F32, "f32_f16table": F32_F16TABLE}
 _ALGO = {"tiled": ALGO_TILED, "plain": ALGO_PLAIN}
-_WMODE = {"linear": _lib.W_LINEAR, "fold": _lib.W_FOLD, "fold_sqrt": _lib.W_FOLD_SQRT}
+_WMODE = {"linear": _lib.W_LINEAR, "fold": _lib.W_FOLD, "fold_sqrt": _lib.W_FOLD_SQRT,
+          "stack": _lib.W_STACK}
 
 
 def _stream(stream):
@@ -103,15 +104,23 @@ class Kernels:
         return int(t.value), int(c.value)
 
     def new_grid(self, device="cuda") -> torch.Tensor:
-        n, ni = self.params["n"], self.params.get("n_images", 1)
-        return torch.zeros((ni, n, n), dtype=self.cplx, device=device)
+        return torch.zeros((self.n_grids, self.params["n"], self.params["n"]), dtype=self.cplx,
+                           device=device)
+
+    @property
+    def n_grids(self) -> int:
+        """Grids per call: one per image, or one per (image, w-stacking layer)."""
+        stacked = self.params.get("w_mode") in ("stack", _lib.W_STACK)
+        layers = max(1, int(self.params.get("n_wlayers", 1) or 1)) if stacked else 1
+        return int(self.params.get("n_images", 1)) * layers
 
 
 def make_kernels(params: dict, stream=None) -> Kernels:
     """wproj_make_kernels.  params keys: n, cell_rad, n_wplanes, w_max, support,
     support_per_plane (list or None), oversample, kernel_image_size, precision
     ("f64" | "f32" | "f32_f16table"), n_images, algorithm ("tiled" | "plain"), tile, chunk,
-    w_mode ("linear" | "fold" | "fold_sqrt")."""
+    w_mode ("linear" | "fold" | "fold_sqrt" | "stack"), n_wlayers (w-stacking layers),
+    accumulate_runs (bool)."""
     P = _lib.Params()
     P.n = int(params["n"])
     P.n_wplanes = int(params["n_wplanes"])
@@ -134,6 +143,8 @@ def make_kernels(params: dict, stream=None) -> Kernels:
     P.chunk = int(params.get("chunk", 0))
     wm = params.get("w_mode", "linear")
     P.w_mode = _WMODE[wm] if isinstance(wm, str) else int(wm)
+    P.n_wlayers = int(params.get("n_wlayers", 0) or 0)
+    P.accumulate_runs = int(bool(params.get("accumulate_runs", False)))
     h = ctypes.c_void_p()
     _lib.check("wproj_make_kernels",
                _lib.lib().wproj_make_kernels(ctypes.byref(P), _stream(stream), ctypes.byref(h)))
@@ -157,7 +168,7 @@ def grid(k: Kernels, uvw: torch.Tensor, vis: torch.Tensor, weight: torch.Tensor,
         k.handle, nvis, _ptr(uvw, "uvw", torch.float64, 3 * nvis), _ptr(vis, "vis", k.cplx, nvis),
         _ptr(weight, "weight", k.real, nvis),
         _ptr(image_offsets, "image_offsets", torch.int64, ni + 1),
-        _ptr(grid_out, "grid", k.cplx, ni * n * n),
+        _ptr(grid_out, "grid", k.cplx, k.n_grids * n * n),
         _ptr(weight_sum, "weight_sum", torch.float64, ni),
         _ptr(counters, "counters", torch.int64, 3),
         _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
@@ -192,7 +203,7 @@ def grid_noalloc(k: Kernels, uvw: torch.Tensor, vis: torch.Tensor, weight: torch
         k.handle, nvis, _ptr(uvw, "uvw", torch.float64, 3 * nvis), _ptr(vis, "vis", k.cplx, nvis),
         _ptr(weight, "weight", k.real, nvis),
         _ptr(image_offsets, "image_offsets", torch.int64, ni + 1),
-        _ptr(grid_out, "grid", k.cplx, ni * n * n),
+        _ptr(grid_out, "grid", k.cplx, k.n_grids * n * n),
         _ptr(weight_sum, "weight_sum", torch.float64, ni),
         _ptr(counters, "counters", torch.int64, 3), _stream(stream)))
 
@@ -215,7 +226,7 @@ def autotune(k: Kernels, uvw: torch.Tensor, vis: torch.Tensor, weight: torch.Ten
         k.handle, nvis, _ptr(uvw, "uvw", torch.float64, 3 * nvis), _ptr(vis, "vis", k.cplx, nvis),
         _ptr(weight, "weight", k.real, nvis),
         _ptr(image_offsets, "image_offsets", torch.int64, ni + 1),
-        _ptr(scratch, "scratch_grid", k.cplx, ni * n * n),
+        _ptr(scratch, "scratch_grid", k.cplx, k.n_grids * n * n),
         _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
     return k.tuning()
 
@@ -230,7 +241,7 @@ def degrid(k: Kernels, uvw: torch.Tensor, model_grid: torch.Tensor, vis_out: tor
         workspace = k.workspace(nvis)
     _lib.check("wproj_degrid", _lib.lib().wproj_degrid(
         k.handle, nvis, _ptr(uvw, "uvw", torch.float64, 3 * nvis),
-        _ptr(model_grid, "model_grid", k.cplx, ni * n * n),
+        _ptr(model_grid, "model_grid", k.cplx, k.n_grids * n * n),
         _ptr(image_offsets, "image_offsets", torch.int64, ni + 1),
         _ptr(vis_out, "vis_out", k.cplx, nvis),
         _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
@@ -245,7 +256,7 @@ def image(k: Kernels, direction: int, grid_buf: torch.Tensor, image_buf: torch.T
     if workspace is None:
         workspace = k.workspace(0)
     _lib.check("wproj_image", _lib.lib().wproj_image(
-        k.handle, int(direction), _ptr(grid_buf, "grid", k.cplx, ni * n * n),
+        k.handle, int(direction), _ptr(grid_buf, "grid", k.cplx, k.n_grids * n * n),
         _ptr(image_buf, "image", k.real, ni * n * n),
         _ptr(weight_sum, "weight_sum", torch.float64, ni),
         _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
@@ -278,12 +289,12 @@ class Plan:
         n, ni = self.k.params["n"], self.k.params.get("n_images", 1)
         _lib.check("wproj_grid_planned", _lib.lib().wproj_grid_planned(
             self.handle, _ptr(vis, "vis", self.k.cplx, self.nvis),
-            _ptr(grid_buf, "grid", self.k.cplx, ni * n * n), _stream(stream)))
+            _ptr(grid_buf, "grid", self.k.cplx, self.k.n_grids * n * n), _stream(stream)))
 
     def degrid(self, model_grid: torch.Tensor, vis_out: torch.Tensor, stream=None):
         n, ni = self.k.params["n"], self.k.params.get("n_images", 1)
         _lib.check("wproj_degrid_planned", _lib.lib().wproj_degrid_planned(
-            self.handle, _ptr(model_grid, "model_grid", self.k.cplx, ni * n * n),
+            self.handle, _ptr(model_grid, "model_grid", self.k.cplx, self.k.n_grids * n * n),
             _ptr(vis_out, "vis_out", self.k.cplx, self.nvis), _stream(stream)))
 
     def free(self):
@@ -326,6 +337,20 @@ def regroup_rows(ant1: torch.Tensor, ant2: torch.Tensor, n_ant: int, stream=None
         _ptr(counts, "counts", torch.int64, n_keys), _ptr(ws, "workspace", torch.uint8), ws.numel(),
         _stream(stream)))
     return perm, start, counts
+
+
+def regroup_channels(perm: torch.Tensor, start: torch.Tensor, counts: torch.Tensor, n_ant: int,
+                     n_chan: int, stream=None) -> torch.Tensor:
+    """wproj_regroup_channels: the visibility permutation (int64 [n_rows * n_chan]) that
+    takes rows regrouped by baseline (regroup_rows) to baseline-, channel-, time-major order."""
+    n_rows = int(perm.shape[0])
+    n_keys = n_ant * (n_ant + 1) // 2 + 1
+    out = torch.empty(n_rows * int(n_chan), dtype=torch.int64, device=perm.device)
+    _lib.check("wproj_regroup_channels", _lib.lib().wproj_regroup_channels(
+        n_rows, int(n_ant), int(n_chan), _ptr(perm, "perm", torch.int64, n_rows),
+        _ptr(start, "start", torch.int64, n_keys), _ptr(counts, "counts", torch.int64, n_keys),
+        _ptr(out, "vis_perm", torch.int64, n_rows * int(n_chan)), _stream(stream)))
+    return out
 
 
 def gather_rows(perm: torch.Tensor, src: torch.Tensor, out: Optional[torch.Tensor] = None,

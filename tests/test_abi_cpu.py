@@ -42,7 +42,9 @@ def _params(**kw):
                                  dict(w_max=-1.0), dict(support=0), dict(support=7, oversample=1),
                                  dict(kernel_image_size=31), dict(precision=7), dict(n_images=0),
                                  dict(algorithm=5), dict(tile=48), dict(chunk=100),
-                                 dict(w_mode=3), dict(w_mode=-1)])
+                                 dict(w_mode=4), dict(w_mode=-1), dict(accumulate_runs=2),
+                                 dict(n_wlayers=2), dict(w_mode=3, n_wlayers=-1),
+                                 dict(w_mode=3, n_wlayers=4097)])
 def test_make_kernels_rejects_invalid_params(bad):
     L = _lib.lib()
     h = ctypes.c_void_p()
@@ -54,7 +56,7 @@ def test_make_kernels_rejects_invalid_params(bad):
 def test_reserved_and_per_plane_support_checked():
     L = _lib.lib()
     P = _params()
-    P.reserved[2] = 1
+    P.reserved[0] = 1
     h = ctypes.c_void_p()
     assert L.wproj_make_kernels(ctypes.byref(P), None, ctypes.byref(h)) == -1
     P = _params()
