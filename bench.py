@@ -43,7 +43,7 @@ HBM_BYTES_PER_VIS_GRID = 16      # one binned record read by the tile gridder
 # WRITE_SIZE x1.000, scale factors from a 512 MiB copy), measured at tile 32 / 8192
 # records per work item on this workload; profiles/tiled_grid_kernel_2048_S8_cfg2.md
 # has the commands and raw values.  Reported only when the run uses that configuration.
-MEASURED_TRAFFIC = {"tile": 32, "chunk": 8192, "bytes": 1129.1e6}
+MEASURED_TRAFFIC = {"tile": 32, "chunk": 8192, "bytes": 890.2e6}
 
 
 def log(*a):
@@ -63,8 +63,9 @@ def parse():
     ap.add_argument("--cpu-single-seconds", type=float, default=10.0,
                     help="work for the single-thread leg of the host oracle baseline")
     ap.add_argument("--no-extra-configs", action="store_true",
-                    help="skip timing the 4096^2 variable-support and 64-image workloads and "
-                         "the Hermitian-fold modes")
+                    help="skip timing the 4096^2 variable-support and 64-image workloads, "
+                         "the Hermitian-fold and w-stacking modes and the run-accumulation "
+                         "measurement")
     ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the step replayed from a captured HIP graph")
     ap.add_argument("--tile", type=int, default=0, help="fix the tile side (skips autotuning)")
@@ -290,7 +291,8 @@ def main():
         # register accumulation over runs of a shared footprint origin (accumulate_runs),
         # on the same visibilities put in baseline, channel, time order by the library
         # (regroup by baseline, then the channel-major visibility permutation and gathers)
-        runs = run_accumulation(W, k, params, a1, a2, n_ant, n_ch, uvw, vis32, wt32, stream, reps)
+        runs = (None if args.no_extra_configs else
+                run_accumulation(W, k, params, a1, a2, n_ant, n_ch, uvw, vis32, wt32, stream, reps))
         del perm, a1, a2
 
     extra = {"phases_ms": per, "tuning": {"tile": tile, "chunk": chunk},
