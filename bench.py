@@ -43,7 +43,7 @@ HBM_BYTES_PER_VIS_GRID = 16      # one binned record read by the tile gridder
 # WRITE_SIZE x1.000, scale factors from a 512 MiB copy), measured at tile 32 / 8192
 # records per work item on this workload; profiles/tiled_grid_kernel_2048_S8_cfg2.md
 # has the commands and raw values.  Reported only when the run uses that configuration.
-MEASURED_TRAFFIC = {"tile": 32, "chunk": 8192, "bytes": 890.2e6}
+MEASURED_TRAFFIC = {"tile": 32, "chunk": 8192, "bytes": 892.6e6}
 
 
 def log(*a):

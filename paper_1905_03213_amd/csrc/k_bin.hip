@@ -11,11 +11,13 @@
 //   scan         exclusive prefix sum of count (Eq. 6);
 //   scatter      record of visibility j goes to offset[key] + slot;
 //   work list    each tile's record range split into chunks of at most `chunk` records.
-// Count atomics are aggregated over runs of a wavefront's lanes that share a key.  With a
-// fixed support (records carry the packed LDS offset and sub-kernel number) the key pass
-// also stores each visibility's key and packed word next to its slot, so the scatter
-// reads 12 bytes instead of the 24-byte uvw and skips the FP64 footprint; otherwise the
-// scatter recomputes the key from the coordinates.
+// Count atomics are aggregated over runs of a wavefront's lanes that share a key, so a
+// record's place inside its bin follows the order in which the runs' atomics land (the
+// bin's contents are fixed, their order is not).  With a fixed support (records carry
+// the packed LDS offset and sub-kernel number) the key pass also stores each
+// visibility's key and packed word next to its slot, so the scatter reads 12 bytes
+// instead of the 24-byte uvw and skips the FP64 footprint; otherwise the scatter
+// computes the footprint again from the coordinates.
 #include <algorithm>
 
 #include "wproj_tiled.h"
@@ -26,33 +28,40 @@ namespace {
 constexpr uint32_t kInvalid = 0xffffffffu;
 constexpr uint32_t kFoldBit = 0x80000000u;
 
-__device__ inline uint64_t lane_mask_lt() {
-  const int lane = threadIdx.x & 63;
-  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
+// Visibilities per thread of the key pass.  A thread issues the loads of all its
+// visibilities first and then all its count atomics before it waits on any, so a wave
+// keeps more loads and atomics in flight than with one visibility per thread.  Two
+// measured fastest: with four the key pass is no faster and the scatter after it is
+// slower (the order in which slots are handed out changes how its scattered writes
+// combine).  The scatter keeps one visibility per thread.
+constexpr int kBinBlock = 256;
+constexpr int kKeyVpt = 2;
 
-// atomicAdd(count[key], 1) for every lane with a key, returning the lane's slot.  Lanes
-// are grouped into runs of consecutive lanes with equal keys (rows of one baseline's
-// channels are adjacent and share tiles and planes, so a wavefront holds a few long
-// runs); the first lane of each run adds the run's length with one atomic, and each lane's
-// slot is its run's returned base plus its distance from the run's first lane.  The cost
-// is a fixed handful of instructions whatever the number of runs; equal keys in separate
-// runs take separate atomics, which leaves the counts and the uniqueness of slots intact.
-// Lanes with key == kInvalid take no part.
-__device__ inline uint32_t run_slot(uint32_t *count, uint32_t key) {
+// Runs of consecutive lanes with equal keys (rows of one baseline's channels are adjacent
+// and share tiles and planes, so a wavefront holds a few long runs).  The first lane of
+// a run adds the run's length to its key's count with one atomic, and each lane's slot
+// is the returned base plus its distance from the run's first lane.  Equal keys in
+// separate runs take separate atomics, which leaves the counts and the uniqueness of
+// slots intact.  Lanes with key == kInvalid take no part.
+struct Run {
+  int leader;    // first lane of this lane's run
+  uint32_t len;  // run length (meaningful in the first lane)
+  bool lead;     // this lane adds the run to its key's count
+};
+
+__device__ inline Run run_of(uint32_t key) {
   const int lane = threadIdx.x & 63;
   const uint32_t prev = __shfl_up(key, 1, 64);
   const bool start = lane == 0 || key != prev;
   const uint64_t starts = __ballot(start);
   const uint64_t upto = (2ull << lane) - 1ull;  // lanes 0..lane (all 64 bits for lane 63)
-  const int leader = 63 - __clzll((long long)(starts & upto));
-  uint32_t got = 0;
-  if (start && key != kInvalid) {
-    const uint64_t after = starts & ~upto;
-    const int next = after ? __ffsll((unsigned long long)after) - 1 : 64;
-    got = atomicAdd(&count[key], (uint32_t)(next - lane));
-  }
-  return __shfl(got, leader, 64) + (uint32_t)(lane - leader);
+  const uint64_t after = starts & ~upto;
+  const int next = after ? __ffsll((unsigned long long)after) - 1 : 64;
+  Run r;
+  r.leader = 63 - __clzll((long long)(starts & upto));
+  r.len = (uint32_t)(next - lane);
+  r.lead = start && key != kInvalid;
+  return r;
 }
 
 // Bin key of a gridded visibility of image img (of its grid: the image, or the image's
@@ -78,74 +87,132 @@ __device__ inline uint32_t record_lds(const Geometry &G, const BinShape &B, cons
   return r;
 }
 
+// Image of every row of the block when one image holds them all (images are contiguous
+// row ranges), else -1; first receives the image of the block's first row (-1 when it
+// is in none).  The arguments are the same in every lane.
+template <int VPT>
+__device__ inline int block_image(const int64_t *off, int n_images, int64_t nvis, int &first) {
+  const int64_t j_first = (int64_t)blockIdx.x * (kBinBlock * VPT);
+  if (j_first >= nvis) {
+    first = -1;
+    return -1;
+  }
+  first = image_of(off, n_images, j_first);
+  const int last = image_of(off, n_images, min(j_first + (int64_t)(kBinBlock * VPT), nvis) - 1);
+  return first >= 0 && first == last ? first : -1;
+}
+
+// Visibility j of thread t of block b in pass i: b 256 VPT + 256 i + t, so each pass of
+// a wavefront covers 64 consecutive visibilities.
+template <int VPT>
+__device__ inline int64_t bin_row(int i) {
+  return (int64_t)blockIdx.x * (kBinBlock * VPT) + i * kBinBlock + threadIdx.x;
+}
+
 // COMPACT: slots holds three arrays of nvis words: slot, key (kInvalid when the
-// visibility is not gridded) and the record's packed first word.
+// visibility is not gridded; a Hermitian-folded visibility has the key's top bit set,
+// keys then stay below 2^31) and the record's packed first word.  Otherwise only the slot.
 template <typename Real, bool COMPACT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kBinBlock)
     key_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
                const Real *__restrict__ wt, const int64_t *__restrict__ img_off,
-               uint32_t *__restrict__ slots, uint32_t *count,
-               double *wsum, unsigned long long *counters) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t key = kInvalid, packed = 0;
-  int cls = kFlagged;
-  int img = -1;
-  bool clamped = false, fold = false;
-  double w = 0.0;
-  if (j < nvis) {
-    img = image_of(img_off, G.n_images, j);
-    if (img >= 0) {
-      Footprint f;
-      const Real wj = wt ? wt[j] : Real(1);
-      cls = classify(G, uvw + 3 * j, wj, f);
-      if (cls == kGridded) {
-        key = bin_key(G, B, img, f);
-        fold = f.fold;
-        if constexpr (COMPACT) packed = record_lds(G, B, f);
-        w = (double)wj;
-        clamped = w_clamped(G, uvw[3 * j + 2]);
-      }
+               int S_fix, uint32_t *__restrict__ slots, uint32_t *count, double *wsum,
+               unsigned long long *counters) {
+  constexpr int V = kKeyVpt;
+  // every load of the thread first
+  double c[V][3];
+  Real wj[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const int64_t j = bin_row<V>(i);
+    c[i][0] = c[i][1] = c[i][2] = 0.0;
+    wj[i] = Real(0);
+    if (j < nvis) {
+      c[i][0] = uvw[3 * j];
+      c[i][1] = uvw[3 * j + 1];
+      c[i][2] = uvw[3 * j + 2];
+      wj[i] = wt ? wt[j] : Real(1);
     }
   }
-  const uint32_t slot = run_slot(count, key);
-  if (j < nvis) {
-    slots[j] = slot;
-    if constexpr (COMPACT) {
-      // a Hermitian-folded visibility keeps its flag in the key's top bit (keys then stay
-      // below 2^31)
-      slots[nvis + j] = fold ? (key | kFoldBit) : key;
-      slots[2 * nvis + j] = packed;
+  int img_b;  // image of the block's first row
+  const int img_all = block_image<V>(img_off, G.n_images, nvis, img_b);
+  // then every footprint (kernel-table lookups included) ...
+  uint32_t key[V], packed[V];
+  bool fold[V];
+  double w_mine = 0.0;
+  unsigned n_drop = 0, n_clamp = 0, n_bad = 0;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const int64_t j = bin_row<V>(i);
+    key[i] = kInvalid;
+    packed[i] = 0;
+    fold[i] = false;
+    int cls = kFlagged;
+    bool clamped = false;
+    if (j < nvis) {
+      const int img = img_all >= 0 ? img_all : image_of(img_off, G.n_images, j);
+      if (img >= 0) {
+        Footprint f;
+        cls = classify(G, c[i], wj[i], f, COMPACT ? S_fix : 0);
+        if (cls == kGridded) {
+          key[i] = bin_key(G, B, img, f);
+          fold[i] = f.fold;
+          if constexpr (COMPACT) packed[i] = record_lds(G, B, f);
+          clamped = w_clamped(G, c[i][2]);
+          // rows of an image other than the block's first row's image (only in blocks
+          // that straddle an image boundary) add their weights to their image's slot
+          if (img == img_b)
+            w_mine += (double)wj[i];
+          else if (wsum)
+            unsafeAtomicAdd(&wsum[(int64_t)img * kSlots + (blockIdx.x & (kSlots - 1))], (double)wj[i]);
+        }
+      }
+    }
+    n_drop += (unsigned)__popcll(__ballot(cls == kDropped));
+    n_bad += (unsigned)__popcll(__ballot(cls == kBadWeight));
+    n_clamp += (unsigned)__popcll(__ballot(clamped));
+  }
+  // ... then every count atomic, and only then the slots
+  Run run[V];
+  uint32_t got[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    run[i] = run_of(key[i]);
+    uint32_t g = 0;
+    if (run[i].lead) g = atomicAdd(&count[key[i]], run[i].len);
+    got[i] = g;
+  }
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const int64_t j = bin_row<V>(i);
+    const uint32_t slot = __shfl(got[i], run[i].leader, 64) + (uint32_t)((threadIdx.x & 63) - run[i].leader);
+    if (j < nvis) {
+      slots[j] = slot;
+      if constexpr (COMPACT) {
+        slots[nvis + j] = fold[i] ? (key[i] | kFoldBit) : key[i];
+        slots[2 * nvis + j] = packed[i];
+      }
     }
   }
   // Counters and weight sums: reduced over the workgroup in LDS, then one atomic per
   // workgroup into one of kSlots partial accumulators (chosen by block index) so that
-  // no address is hit by many workgroups; finalize_kernel adds the slots up.  Rows of
-  // an image other than the workgroup's first row's image (only at image boundaries)
-  // add their weights to their own image's slot directly.
-  __shared__ double s_w[4];
-  __shared__ unsigned s_c[3][4];
+  // no address is hit by many workgroups; finalize_kernel adds the slots up.
+  __shared__ double s_w[kBinBlock / 64];
+  __shared__ unsigned s_c[3][kBinBlock / 64];
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int acc_slot = blockIdx.x & (kSlots - 1);
-  const int64_t j_first = (int64_t)blockIdx.x * blockDim.x;
-  const int img_b = j_first < nvis ? image_of(img_off, G.n_images, j_first) : -1;
-  const uint64_t dropped = __ballot(cls == kDropped);
-  const uint64_t bad = __ballot(cls == kBadWeight);
-  const uint64_t clamp = __ballot(clamped);
-  const bool mine = key != kInvalid && img == img_b;
-  double wv = wave_sum(mine ? w : 0.0);
-  if (wsum && key != kInvalid && img != img_b) unsafeAtomicAdd(&wsum[(int64_t)img * kSlots + acc_slot], w);
+  const double wv = wave_sum(w_mine);
   if (lane == 0) {
     s_w[wid] = wv;
-    s_c[0][wid] = (unsigned)__popcll(dropped);
-    s_c[1][wid] = (unsigned)__popcll(clamp);
-    s_c[2][wid] = (unsigned)__popcll(bad);
+    s_c[0][wid] = n_drop;
+    s_c[1][wid] = n_clamp;
+    s_c[2][wid] = n_bad;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
     double tw = 0.0;
     unsigned c0 = 0, c1 = 0, c2 = 0;
-    for (int i = 0; i < nw; ++i) {
+    for (int i = 0; i < kBinBlock / 64; ++i) {
       tw += s_w[i];
       c0 += s_c[0][i];
       c1 += s_c[1][i];
@@ -161,9 +228,12 @@ __global__ void __launch_bounds__(256)
 }
 
 // COMPACT: the key pass stored each visibility's key and packed first word (fixed
-// support S_fix, whose sub-kernel number n starts at tap n S_fix^2).
+// support S_fix, whose sub-kernel number n starts at tap n S_fix^2); otherwise the
+// footprint is computed again from the same inputs, with the same outcome.  A
+// visibility's key is loaded first, so that the bin offset it indexes is fetched while
+// the rest of the record's inputs arrive; rows that are not gridded load nothing more.
 template <typename Real, typename Cplx, typename Rec, bool COMPACT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kBinBlock)
     scatter_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
                    const Cplx *__restrict__ vis, const Real *__restrict__ wt,
                    const int64_t *__restrict__ img_off, const uint32_t *__restrict__ slots,
@@ -184,7 +254,6 @@ __global__ void __launch_bounds__(256)
   } else {
     const int img = image_of(img_off, G.n_images, j);
     if (img < 0) return;
-    // same inputs, same outcome (and key) as the key pass
     Footprint f;
     const Real w = wt ? wt[j] : Real(1);
     if (classify(G, uvw + 3 * j, w, f) != kGridded) return;
@@ -408,22 +477,23 @@ hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, c
   if ((e = launch_fill_u32((uint32_t *)W.cslots, 2 * 3 * kSlots, 0u, s)) != hipSuccess) return e;
   double *wpart = wsum ? W.wslots : nullptr;
   auto *cnt = counters ? W.cslots : nullptr;
-  const dim3 grid(nblk(nvis, 256)), block(256);
+  const dim3 key_grid(nblk(nvis, kBinBlock * kKeyVpt)), grid(nblk(nvis, kBinBlock)), block(kBinBlock);
   const bool compact = B.pack_sub != 0;
+  const int S_fix = k->s_max;  // the fixed support of packed records
   if (k->params.precision == WPROJ_F64) {
     if (compact)
-      hipLaunchKernelGGL((key_kernel<double, true>), grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
-                         img_off, W.slots, W.count, wpart, cnt);
+      hipLaunchKernelGGL((key_kernel<double, true>), key_grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
+                         img_off, S_fix, W.slots, W.count, wpart, cnt);
     else
-      hipLaunchKernelGGL((key_kernel<double, false>), grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
-                         img_off, W.slots, W.count, wpart, cnt);
+      hipLaunchKernelGGL((key_kernel<double, false>), key_grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
+                         img_off, S_fix, W.slots, W.count, wpart, cnt);
   } else {
     if (compact)
-      hipLaunchKernelGGL((key_kernel<float, true>), grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
-                         img_off, W.slots, W.count, wpart, cnt);
+      hipLaunchKernelGGL((key_kernel<float, true>), key_grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
+                         img_off, S_fix, W.slots, W.count, wpart, cnt);
     else
-      hipLaunchKernelGGL((key_kernel<float, false>), grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
-                         img_off, W.slots, W.count, wpart, cnt);
+      hipLaunchKernelGGL((key_kernel<float, false>), key_grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
+                         img_off, S_fix, W.slots, W.count, wpart, cnt);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (wsum || counters) {
@@ -433,7 +503,6 @@ hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, c
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = launch_exclusive_scan(W.count, W.offset, B.n_keys, W.scan_tmp, s)) != hipSuccess) return e;
-  const int S_fix = k->s_max;
   if (k->params.precision == WPROJ_F64) {
     if (compact)
       hipLaunchKernelGGL((scatter_kernel<double, double2, RecordF64, true>), grid, block, 0, s, G, B, nvis,

@@ -113,8 +113,10 @@ __device__ inline bool axis_footprint(const Geometry &G, double coord, int S, in
   return true;
 }
 
+// S_uniform > 0: every plane has that support (no table lookup).
 template <typename WT>
-__device__ inline int classify(const Geometry &G, const double *uvw, WT wt, Footprint &f) {
+__device__ inline int classify(const Geometry &G, const double *uvw, WT wt, Footprint &f,
+                               int S_uniform = 0) {
   if (wt == WT(0)) return kFlagged;
   if (!(isfinite((double)wt) && wt > WT(0))) return kBadWeight;
   double u = uvw[0], v = uvw[1], w = uvw[2];
@@ -129,7 +131,7 @@ __device__ inline int classify(const Geometry &G, const double *uvw, WT wt, Foot
   }
   f.layer = G.w_mode == WPROJ_W_STACK ? layer_residual(G, w) : 0;
   f.p = plane_of(G, w);
-  const int S = G.supp[f.p];
+  const int S = S_uniform > 0 ? S_uniform : G.supp[f.p];
   if (!axis_footprint(G, u, S, f.x0, f.ou)) return kDropped;
   if (!axis_footprint(G, v, S, f.y0, f.ov)) return kDropped;
   return kGridded;

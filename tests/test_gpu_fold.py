@@ -78,13 +78,14 @@ def test_fold_footprints_match_oracle(mode):
     k.free()
 
 
+# the plain path is the FP64 comparison path: it runs in FP64 only
+ALGO_PREC = [("tiled", "f64"), ("tiled", "f32"), ("tiled", "f32_f16table"), ("plain", "f64")]
+
+
 @pytest.mark.parametrize("mode", MODES)
-@pytest.mark.parametrize("prec", ["f64", "f32", "f32_f16table"])
 @pytest.mark.parametrize("which", ["cfg1", "cfg1w", "tracks"])
-@pytest.mark.parametrize("algo", ["tiled", "plain"])
-def test_fold_grid_matches_oracle(algo, which, prec, mode):
-    if algo == "plain" and prec != "f64":
-        pytest.skip("the plain path is the FP64 comparison path")
+@pytest.mark.parametrize("algo,prec", ALGO_PREC)
+def test_fold_grid_matches_oracle(algo, prec, which, mode):
     wl = _wl(which)
     uvw, vis, wt = planted(wl)
     params = {**wl.params, "precision": prec, "algorithm": algo, "w_mode": mode}

@@ -67,12 +67,13 @@ def test_stack_footprints_match_oracle():
     k.free()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "f32_f16table"])
+# the plain path is the FP64 comparison path: it runs in FP64 only
+ALGO_PREC = [("tiled", "f64"), ("tiled", "f32"), ("tiled", "f32_f16table"), ("plain", "f64")]
+
+
 @pytest.mark.parametrize("which", ["cfg1w", "tracks"])
-@pytest.mark.parametrize("algo", ["tiled", "plain"])
-def test_stack_grid_and_image_match_oracle(algo, which, prec):
-    if algo == "plain" and prec != "f64":
-        pytest.skip("the plain path is the FP64 comparison path")
+@pytest.mark.parametrize("algo,prec", ALGO_PREC)
+def test_stack_grid_and_image_match_oracle(algo, prec, which):
     wl, params = _params(which, prec, algo)
     uvw, vis, wt = planted(wl)
     G, sw, cnt, host = run_grid(params, uvw, vis, wt)
