@@ -77,6 +77,9 @@ def parse():
                     help="only sweep the binned gridding call over full support 3..16 (2048^2) and "
                          "image size 128..4096 (support 8) at a fixed 1e-5 rad cell, FP32 and FP64, "
                          "on the benchmark's visibilities; one JSON line per point")
+    ap.add_argument("--degrid-only", action="store_true",
+                    help="only degrid the benchmark rows --steps times (FP32 tables, --tile or 32, "
+                         "chunk 8192): the command the degridder's counter runs profile")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB device buffer 4 times (a kernel of known traffic "
                          "for scaling hardware byte counters) and exit")
@@ -108,6 +111,23 @@ def main():
         return
     if args.sweep:
         sweep(args, dev)
+        return
+    if args.degrid_only:
+        wl = synth.cfg2(device=dev, precision="f32", hours=args.hours)
+        k = W.make_kernels({**wl.params, "precision": "f32", "algorithm": "tiled",
+                            "tile": args.tile or 32, "chunk": 8192})
+        n = wl.params["n"]
+        model = torch.zeros((1, n, n), dtype=torch.float32, device=dev)
+        model[0, n // 2 + 10, n // 2 - 30] = 1.0
+        g = k.new_grid()
+        ws = k.workspace(wl.nvis)
+        W.image(k, W.IMAGE_TO_GRID, g, model, workspace=ws)
+        out = torch.empty(wl.nvis, dtype=torch.complex64, device=dev)
+        for _ in range(args.steps):
+            W.degrid(k, wl.uvw, g, out, workspace=ws)
+        torch.cuda.synchronize()
+        print(json.dumps({"degrid_launches": args.steps, "rows": wl.nvis}), flush=True)
+        k.free()
         return
     lds_rates = measure_lds_peak()
     # the gridder's LDS traffic is a 64-bit read-add-write of each footprint cell: its

@@ -741,7 +741,9 @@ int wproj_degrid(const wproj_kernels *k, int64_t nvis, const double *uvw, const 
                 (long long)B.n_keys);
   BinWorkspace W;
   carve(k, nvis, (char *)workspace, W);
-  B.pitch = degrid_pitch(k, B.tile);  // records binned for the degridder's own tile layout
+  // records binned for the degridder's own tile layout: the gridder's pitch for the
+  // one-tap-per-lane kernel, an odd pitch for the row-per-lane kernel
+  if (!tap_lane_degrid(k, B)) B.pitch = degrid_pitch(k, B.tile);
   {
     PhaseTimer pt(k, WPROJ_PHASE_BIN, s);
     HIP_TRY(launch_bin(k, B, nvis, uvw, nullptr, nullptr, image_offsets, nullptr, nullptr, W, s));

@@ -6,14 +6,17 @@
 // (S_max - 1)-cell halo into its private LDS with coalesced row loads, and then serves
 // every record's footprint from LDS instead of gathering it from HBM.
 //
-// Records go 8 at a time, a group of 8 lanes per record; lane r of a group takes
-// footprint rows kv = r, r + 8, ...: a row's S taps are contiguous in the sub-kernel and
-// its S cells contiguous in the LDS tile.  The group's partial sums are combined across
-// its 8 lanes and the first lane of the group stores V_j.  Binned for degridding alone,
-// the tile copy has an odd row pitch (degrid_pitch), so the rows of a footprint start on
-// different LDS banks whatever the bank count; plans share their records with the
-// gridder and keep its pitch (an odd multiple of 8 cells, which suits the gridder's
-// one-tap-per-lane pattern).
+// Two kernels serve the records.  With FP32 arithmetic and tables and a fixed support
+// up to 8, tap_lane_degrid_kernel (below) gives each lane one tap of a record, as the
+// gridder does, and sums a record's products across lanes.  Otherwise (FP64, FP16
+// tables, larger or per-plane supports) records go 8 at a time, a group of 8 lanes per
+// record; lane r of a group takes footprint rows kv = r, r + 8, ...: a row's S taps are
+// contiguous in the sub-kernel and its S cells contiguous in the LDS tile.  The group's
+// partial sums are combined across its 8 lanes and the first lane of the group stores
+// V_j.  Binned for that kernel alone, the tile copy has an odd row pitch (degrid_pitch),
+// so the rows of a footprint start on different LDS banks whatever the bank count; plans
+// share their records with the gridder and keep its pitch (an odd multiple of 8 cells,
+// which suits the one-tap-per-lane pattern).
 #include <algorithm>
 #include <type_traits>
 
@@ -34,6 +37,8 @@ __device__ inline float2 tap_at(const half2c *t, uint32_t i) {
 }
 
 constexpr int kDegridWaves = 4;
+// Wavefronts sharing one work item (and one tile copy) in the one-tap-per-lane degridder.
+constexpr int kTeamWaves = 4;
 
 // (re, im) += conj(k) m as four fused multiply-adds (written out, because the compiler
 // otherwise forms a product, a fused multiply-add and an add per component)
@@ -221,6 +226,233 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
   }
 }
 
+// Fixed support S <= 8 with FP32 arithmetic and FP32 tables, packed records: the
+// gridder's layout run backwards.  A work item is taken by a team of kTeamWaves
+// wavefronts that share one tile copy, each taking every kTeamWaves-th batch of 64
+// records (a copy per wavefront would leave room for 12 wavefronts per CU at tile 32;
+// measured 1.95 -> 1.82 ms on the 2048^2 benchmark rows).  Records go in pairs, one per
+// half wavefront: lane
+// j of a half takes taps j and h + j (h = ceil(S^2 / 2)) of its half's record, which one
+// load from the pair-ordered table brings (entries 2j and 2j + 1 of a sub-kernel), and
+// reads the two footprint cells they weight from the tile copy.  A half wavefront's
+// cells are four footprint rows of one record, which the gridder's row pitch keeps free
+// of bank conflicts (the records are binned with it).  Each lane sums conj(tap) * cell
+// over its two taps; a record's prediction is the sum of those partial sums over its
+// half wavefront.  The sums of a batch of 64 records are formed together by a
+// transpose-reduce: each step combines two values into one, halving both the values a
+// lane holds and the lanes each value spans (lanes 16 apart through the quarter-
+// wavefront swap, then 8, 4, 2 and 1 apart through DPP moves), so that lane L ends with
+// the prediction of the batch's record bitrev6(L).  The steps run as the pairs arrive,
+// in the order of a binary counter over them, and a lane holds one pending value per step.
+template <int STEP>
+__device__ inline float combine(float a, float b, int lane) {
+  if constexpr (STEP == 1) {  // lanes 16 apart: rows 1, 3 of a with rows 0, 2 of b
+    const auto x = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(x[0]) + __uint_as_float(x[1]);
+  } else {
+    // lanes with the step's bit set keep b and receive the partner's b; the others keep a
+    constexpr int bit = 5 - STEP;  // 8, 4, 2, 1 lanes apart
+    constexpr int ctrl = STEP == 2 ? 0x128 : STEP == 3 ? 0x141 : STEP == 4 ? 0x4E : 0xB1;
+    const bool hi = (lane >> bit) & 1;
+    const float send = hi ? a : b, keep = hi ? b : a;
+    return keep + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), ctrl, 0xF, 0xF, false));
+  }
+}
+
+// The lane's two taps of its record from one pair-ordered load (FP32 table).
+__device__ inline void tap_pair(const TapPair<float2>::Raw &v, float2 &a, float2 &b) {
+  a = make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+  b = make_float2(__uint_as_float(v[2]), __uint_as_float(v[3]));
+}
+
+template <typename Tab, int S>
+__global__ void __launch_bounds__(64 * kTeamWaves)
+    tap_lane_degrid_kernel(Geometry G, BinShape B, int pitch, int rows, int wave_lds,
+                           const Tab *__restrict__ tab, uint32_t tab_bytes,
+                           const RecordF32 *__restrict__ rec, const WorkItem *__restrict__ items,
+                           const uint32_t *__restrict__ order, const uint32_t *__restrict__ n_items_ptr,
+                           uint32_t *counter, const float2 *__restrict__ model, float2 *__restrict__ out) {
+  static_assert(S * S <= 64, "one pass of 64 taps");
+  using P = TapPair<Tab>;
+  using Raw = typename P::Raw;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ uint32_t s_item;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  float2 *tile = reinterpret_cast<float2 *>(smem_raw);
+  const uint32_t n_items = *n_items_ptr;
+  const int64_t cells = (int64_t)G.n * G.n;
+  const int tiles_per_img = B.ntx * B.nty;
+  const bool folding = G.w_mode != WPROJ_W_LINEAR;
+  const __amdgpu_buffer_rsrc_t tab_rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void *)tab, (short)0, (int)tab_bytes, kBufferWord3);
+  constexpr int kN = S * S, kH = (kN + 1) / 2;
+  constexpr uint32_t kSubBytes = (uint32_t)(2 * kH) * P::kTapBytes;
+  const int half = lane >> 5, j = lane & 31;
+  uint32_t upper = half ? 0xffffffffu : 0u;
+  asm volatile("" : "+v"(upper));  // keeps the selects below one vector AND each
+  // taps j and h + j of the half's record, where they exist (lanes past the sub-kernel
+  // read entry pair 0 and contribute nothing)
+  const bool on1 = j < kH, on2 = j < kN - kH;
+  uint32_t p_pair = (on1 ? (uint32_t)(2 * j) : 0u) * P::kTapBytes;
+  asm volatile("" : "+v"(p_pair));
+  // byte offsets (from smem_raw) of the lane's two cells in a footprint whose first cell
+  // is the copy's cell 0
+  const uint32_t tile0 = 0u;
+  const int t1 = on1 ? j : 0, t2 = on2 ? kH + j : 0;
+  uint32_t c1 = tile0 + (uint32_t)((t1 / S) * pitch + t1 % S) * 8u;
+  uint32_t c2 = tile0 + (uint32_t)((t2 / S) * pitch + t2 % S) * 8u;
+  asm volatile("" : "+v"(c1));
+  asm volatile("" : "+v"(c2));
+  // lane L ends with record bitrev6(L) of the batch
+  const int mine = (int)(__builtin_bitreverse32((uint32_t)lane) >> 26);
+
+  for (;;) {
+    __syncthreads();  // every wave is done with the previous tile and item
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t it = s_item;
+    if (it >= n_items) break;
+    const WorkItem w = items[order[it]];  // largest items first
+    const int img = (int)(w.tile / (uint32_t)tiles_per_img);
+    const int rt = (int)(w.tile - (uint32_t)img * tiles_per_img);
+    const int ty = rt / B.ntx, tx = rt - ty * B.ntx;
+    const int ox = tx * B.tile, oy = ty * B.tile;
+    const float2 *mimg = model + cells * img;
+    for (int i = threadIdx.x; i < rows * rows; i += blockDim.x) {
+      const int ry = i / rows, rx = i - ry * rows;
+      const int gy = oy + ry, gx = ox + rx;
+      float2 v = make_float2(0.0f, 0.0f);
+      if (gy < G.n && gx < G.n) v = mimg[(int64_t)gy * G.n + gx];
+      tile[ry * pitch + rx] = v;
+    }
+    __syncthreads();
+
+    const uint32_t n_rec = w.end - w.begin;
+    // records 64 at a time, lane i holding record i of the batch; padding lanes repeat
+    // the last record and their predictions are not stored
+    auto load_batch = [&](uint32_t b, RecordF32 &dst) {
+      const uint32_t i = b + (uint32_t)lane;
+      dst = rec[w.begin + (i < n_rec ? i : n_rec - 1)];
+    };
+    // the lane's two taps of record k (lower half) or k + 1 (upper half) of the batch
+    // (sub-kernel numbers above the LDS offsets)
+    auto fetch = [&](const RecordF32 &c, int k) {
+      const uint32_t a = (bcast(c.lds, k) >> kLdsBits) * kSubBytes;
+      const uint32_t d = (bcast(c.lds, k + 1) >> kLdsBits) * kSubBytes - a;
+      return P::load(tab_rsrc, a + (upper & d) + p_pair);
+    };
+    // the lane's two footprint cells of record k (lower half) or k + 1 (upper half)
+    auto cells = [&](const RecordF32 &c, int k, float2 &m1, float2 &m2) {
+      const uint32_t a = (bcast(c.lds, k) & kLdsMask) * 8u;
+      const uint32_t d = (bcast(c.lds, k + 1) & kLdsMask) * 8u - a;
+      const uint32_t sel = (upper & d) + a;
+      m1 = *reinterpret_cast<const float2 *>(smem_raw + (c1 + sel));
+      m2 = *reinterpret_cast<const float2 *>(smem_raw + (c2 + sel));
+    };
+    // sum of conj(tap) * cell over the lane's two taps
+    auto partial = [&](const Raw &v, const float2 &m1, const float2 &m2, float &re, float &im) {
+      float2 ta, tb;
+      tap_pair(v, ta, tb);
+      if constexpr (kN < 64) {
+        if (!on1) ta = make_float2(0.0f, 0.0f);
+        if (!on2) tb = make_float2(0.0f, 0.0f);
+      }
+      re = __builtin_fmaf(ta.x, m1.x, ta.y * m1.y);
+      re = __builtin_fmaf(tb.x, m2.x, re);
+      re = __builtin_fmaf(tb.y, m2.y, re);
+      im = __builtin_fmaf(ta.x, m1.y, -(ta.y * m1.x));
+      im = __builtin_fmaf(tb.x, m2.y, im);
+      im = __builtin_fmaf(-tb.y, m2.x, im);
+    };
+    constexpr uint32_t kStep = 64u * kTeamWaves;
+    RecordF32 cur;
+    if ((uint32_t)wid * 64u < n_rec) load_batch((uint32_t)wid * 64u, cur);
+    for (uint32_t b = (uint32_t)wid * 64u; b < n_rec; b += kStep) {
+      RecordF32 nxt;
+      const bool more = b + kStep < n_rec;
+      if (more) load_batch(b + kStep, nxt);
+      // pending value of each step (1 .. 5), real and imaginary parts; [0]: the result
+      float pr[6], pi[6];
+      // pairs in groups of 4; a group's taps and cells load while the previous group is
+      // reduced
+      Raw c[2][4];
+      float2 m[2][4][2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        c[0][i] = fetch(cur, 2 * i);
+        cells(cur, 2 * i, m[0][i][0], m[0][i][1]);
+      }
+#pragma unroll
+      for (int g = 0; g < 8; ++g) {
+        if (g + 1 < 8) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) c[(g + 1) & 1][i] = fetch(cur, 8 * (g + 1) + 2 * i);
+        }
+        if (g + 1 < 8) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            cells(cur, 8 * (g + 1) + 2 * i, m[(g + 1) & 1][i][0], m[(g + 1) & 1][i][1]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int pair = 4 * g + i;
+          // records 2 pair (lower half) and 2 pair + 1 (upper half)
+          float vr, vi;
+          partial(c[g & 1][i], m[g & 1][i][0], m[g & 1][i][1], vr, vi);
+          // carry: step s combines the pending value (the earlier pairs) with this one
+#pragma unroll
+          for (int s = 1; s <= 5; ++s) {
+            if (((pair >> (s - 1)) & 1) == 0) {
+              pr[s] = vr;
+              pi[s] = vi;
+              break;
+            }
+            switch (s) {
+              case 1: vr = combine<1>(pr[1], vr, lane); vi = combine<1>(pi[1], vi, lane); break;
+              case 2: vr = combine<2>(pr[2], vr, lane); vi = combine<2>(pi[2], vi, lane); break;
+              case 3: vr = combine<3>(pr[3], vr, lane); vi = combine<3>(pi[3], vi, lane); break;
+              case 4: vr = combine<4>(pr[4], vr, lane); vi = combine<4>(pi[4], vi, lane); break;
+              default: vr = combine<5>(pr[5], vr, lane); vi = combine<5>(pi[5], vi, lane); break;
+            }
+            if (s == 5) {
+              pr[0] = vr;
+              pi[0] = vi;
+            }
+          }
+        }
+      }
+      const uint32_t row = (uint32_t)__shfl((int)get_row(cur), mine, 64);
+      const bool fold = folding && __shfl(cur.wr, mine, 64) < 0.0f;
+      if (b + (uint32_t)mine < n_rec) out[row] = make_float2(pr[0], fold ? -pi[0] : pi[0]);
+      if (more) cur = nxt;
+    }
+  }
+}
+
+template <typename Tab, int S>
+hipError_t launch_tap_lane(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
+                           const BinWorkspace &W, const void *model, void *out, hipStream_t s) {
+  auto kern = tap_lane_degrid_kernel<Tab, S>;
+  const int wpb = kTeamWaves;
+  const size_t lds = ts.lds_bytes;
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  if (!k->d_tab_pair || k->pair_stride != pair_table_stride(S)) return hipErrorInvalidValue;
+  const int64_t n_sub = (int64_t)k->params.n_wplanes * k->params.oversample * k->params.oversample;
+  const int wave_lds = (int)(ts.lds_bytes / sizeof(float2));
+  hipLaunchKernelGGL(kern, dim3((unsigned)(k->n_cu * per_cu)), dim3(64 * wpb), lds, s, k->geo, B,
+                     ts.pitch, ts.rows, wave_lds, (const Tab *)k->d_tab_pair,
+                     (uint32_t)(n_sub * k->pair_stride * (int64_t)sizeof(Tab)), (const RecordF32 *)W.rec,
+                     W.items, W.order, W.choff + B.n_tiles, W.counter, (const float2 *)model, (float2 *)out);
+  return hipGetLastError();
+}
+
 template <typename Real, typename Rec, typename Tab, int S>
 hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
                       const BinWorkspace &W, const void *model, void *out, hipStream_t s) {
@@ -262,7 +494,23 @@ hipError_t dispatch(const wproj_kernels *k, const BinShape &B, const TileShape &
   return launch_one<Real, Rec, Tab, 0>(k, B, ts, W, model, out, s);
 }
 
+template <typename Tab, int S>
+hipError_t dispatch_tap_lane(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
+                             const BinWorkspace &W, const void *model, void *out, hipStream_t s) {
+  if constexpr (S > 8) {
+    return hipErrorInvalidValue;
+  } else {
+    if (k->s_max == S) return launch_tap_lane<Tab, S>(k, B, ts, W, model, out, s);
+    return dispatch_tap_lane<Tab, S + 1>(k, B, ts, W, model, out, s);
+  }
+}
+
 }  // namespace
+
+bool tap_lane_degrid(const wproj_kernels *k, const BinShape &B) {
+  return k->params.precision == WPROJ_F32 && B.pack_sub && k->s_max <= 8 && k->d_tab_pair != nullptr &&
+         k->pair_stride == pair_table_stride(k->s_max);
+}
 
 hipError_t launch_tiled_degrid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
                                const void *model_grid, void *vis_out, int64_t nvis, hipStream_t s) {
@@ -275,6 +523,7 @@ hipError_t launch_tiled_degrid(const wproj_kernels *k, const BinShape &B, const 
   hipError_t e = launch_fill_u32((uint32_t *)vis_out, words, 0u, s);
   if (e != hipSuccess) return e;
   if ((e = launch_fill_u32(W.counter, 1, 0u, s)) != hipSuccess) return e;
+  if (tap_lane_degrid(k, B)) return dispatch_tap_lane<float2, kMinFixedSupport>(k, B, ts, W, model_grid, vis_out, s);
   switch (k->params.precision) {
     case WPROJ_F64:
       return dispatch<double, RecordF64, double2>(k, B, ts, W, model_grid, vis_out, s);

@@ -72,6 +72,63 @@ __host__ __device__ inline uint32_t get_row(const RecordF64 &r) {
   return j;
 }
 
+// gfx9 buffer descriptor word 3: 32-bit data format, no swizzle
+constexpr int kBufferWord3 = 0x00020000;
+
+// Paired tap fetch (FP32 arithmetic): one load brings two table entries per lane, lanes
+// 0-31 for the first record of a pair and lanes 32-63 for the second, so a pair of
+// records costs one wide load instead of two narrow ones.  A swap of the upper half of
+// the first entries with the lower half of the second entries (v_permlane32_swap, a
+// VALU operation) then leaves every lane with the same tap of both records.
+template <typename Tab> struct TapPair;
+template <> struct TapPair<float2> {
+  typedef uint32_t Raw __attribute__((ext_vector_type(4)));
+  static constexpr uint32_t kTapBytes = 8;
+  __device__ static Raw load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
+  }
+  __device__ static void split(const Raw &v, float2 &first, float2 &second) {
+    const uint32_t a_re = v[0], a_im = v[1], b_re = v[2], b_im = v[3];
+    const auto re = __builtin_amdgcn_permlane32_swap(a_re, b_re, false, false);
+    const auto im = __builtin_amdgcn_permlane32_swap(a_im, b_im, false, false);
+    const uint32_t f_re = re[0], s_re = re[1], f_im = im[0], s_im = im[1];
+    first = make_float2(__uint_as_float(f_re), __uint_as_float(f_im));
+    second = make_float2(__uint_as_float(s_re), __uint_as_float(s_im));
+  }
+};
+template <> struct TapPair<half2c> {
+  typedef uint32_t Raw __attribute__((ext_vector_type(2)));
+  static constexpr uint32_t kTapBytes = 4;
+  __device__ static Raw load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    return __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+  }
+  __device__ static void split(const Raw &v, float2 &first, float2 &second) {
+    const uint32_t a = v[0], b = v[1];
+    const auto x = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    const uint32_t f = x[0], s = x[1];
+    half2c hf, hs;
+    __builtin_memcpy(&hf, &f, 4);
+    __builtin_memcpy(&hs, &s, 4);
+    first = make_float2((float)hf.re, (float)hf.im);
+    second = make_float2((float)hs.re, (float)hs.im);
+  }
+};
+template <typename Tab> constexpr bool kPairedTab = std::is_same_v<Tab, float2> || std::is_same_v<Tab, half2c>;
+
+// Wave-uniform broadcast of lane j's value (v_readlane).
+__device__ inline uint32_t bcast(uint32_t v, int j) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, j);
+}
+__device__ inline float bcast(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+__device__ inline double bcast(double v, int j) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), j);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Binning geometry: tiles of `tile` cells, ntx x nty per image, kw keys per tile
 // (n_wplanes when the plane is part of the key, else 1).
 struct BinShape {
@@ -143,6 +200,10 @@ hipError_t launch_tiled_grid(const wproj_kernels *k, const BinShape &B, const Bi
                              void *grid, hipStream_t s, const void *vis = nullptr);
 hipError_t launch_tile_reduce(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
                               void *grid, hipStream_t s);
+// Whether launch_tiled_degrid takes the one-tap-per-lane degridder (FP32 arithmetic and
+// tables, packed records of a fixed support up to 8, the pair-ordered table); its
+// records are binned with the gridder's row pitch.
+bool tap_lane_degrid(const wproj_kernels *k, const BinShape &B);
 hipError_t launch_tiled_degrid(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W,
                                const void *model_grid, void *vis_out, int64_t nvis, hipStream_t s);
 
