@@ -38,7 +38,8 @@ S = 8
 LDS_BYTES_PER_VIS = S * S * 16   # complex FP32 read-modify-write per tap
 LDS_READ_BYTES_PER_VIS_DEGRID = S * S * 8  # degridding reads one complex FP32 model cell per tap
 FLOPS_PER_VIS = S * S * 8        # complex multiply-add per tap
-HBM_BYTES_PER_VIS_GRID = 16      # one binned record read by the tile gridder
+HBM_BYTES_PER_VIS_GRID = 12      # one binned record read by the tile gridder
+TAP_BYTES_PER_VIS = S * S * 8    # complex FP32 taps returned to registers by 16-byte loads
 # HBM bytes per launch of tiled_grid_kernel from hardware counters (FETCH_SIZE x2.000 +
 # WRITE_SIZE x1.000, scale factors from a 512 MiB copy), measured at tile 32 / 8192
 # records per work item on this workload; profiles/tiled_grid_kernel_2048_S8_cfg2.md
@@ -135,6 +136,11 @@ def main():
     peak_lds = lds_rates["read_add_write"]
     peak_lds_read = lds_rates["read"]
     log(f"LDS rate (measured): { {k: round(v / 1e12, 2) for k, v in lds_rates.items()} } TB/s")
+    # the tap fetches of the gridder and degridder return through the vector-memory path;
+    # both kernels load 16 bytes per lane (two taps)
+    vmem_rates = measure_vmem_peak()
+    peak_vmem = vmem_rates["16B"]
+    log(f"L1 return rate (measured): { {k: round(v / 1e12, 2) for k, v in vmem_rates.items()} } TB/s")
     t0 = time.time()
     wl = synth.cfg2(device=dev, precision="f32", hours=args.hours)
     nvis = wl.nvis
@@ -241,6 +247,14 @@ def main():
         "alu_frac": FLOPS_PER_VIS * n_valid / t_grid / PEAK_FP32,
         "alu_peak_tflops": PEAK_FP32 / 1e12,
         "hbm_frac": HBM_BYTES_PER_VIS_GRID * n_valid / t_grid / PEAK_HBM,
+        # the taps (64 x 8 bytes per visibility) come back from L1 through the vector-memory
+        # path, which hardware counters show nearly always busy in this kernel
+        "vmem": {"bytes_per_vis": TAP_BYTES_PER_VIS,
+                 "achieved": TAP_BYTES_PER_VIS * n_valid / t_grid / 1e9,
+                 "peak": peak_vmem / 1e9, "unit": "GB/s",
+                 "frac": TAP_BYTES_PER_VIS * n_valid / t_grid / peak_vmem,
+                 "peak_source": "measured on the device: wproj_measure_vmem, 16-byte buffer loads per lane from L1",
+                 "peak_by_width": {k: v / 1e9 for k, v in vmem_rates.items()}},
     }
 
     if not args.step_only:
@@ -322,9 +336,11 @@ def main():
     if not args.step_only:
         extra.update({
             "degrid": {"ms": degrid_ms, "bin_ms": degrid_bin_ms, "mvis_per_s": n_valid / degrid_ms / 1e3,
-                       "kernel": "tiled_degrid_kernel",
+                       "kernel": "tap_lane_degrid_kernel",
                        "lds_read_bytes_per_vis": LDS_READ_BYTES_PER_VIS_DEGRID,
-                       "lds_frac": LDS_READ_BYTES_PER_VIS_DEGRID * n_valid / (degrid_ms * 1e-3) / peak_lds_read},
+                       "lds_frac": LDS_READ_BYTES_PER_VIS_DEGRID * n_valid / (degrid_ms * 1e-3) / peak_lds_read,
+                       "tap_bytes_per_vis": TAP_BYTES_PER_VIS,
+                       "vmem_frac": TAP_BYTES_PER_VIS * n_valid / (degrid_ms * 1e-3) / peak_vmem},
             "planned": {"grid_ms": planned_grid_ms, "grid_mvis_per_s": n_valid / planned_grid_ms / 1e3,
                         "degrid_ms": planned_degrid_ms},
             "run_accumulation": runs,
@@ -635,6 +651,14 @@ def run_accumulation(W, k, params, a1, a2, n_ant, n_ch, uvw, vis, wt, stream, re
             kr.free()
     log(f"run accumulation: {out}")
     return out
+
+
+def measure_vmem_peak():
+    """The device's rate (bytes/s) of L1-resident buffer loads of 4, 8 and 16 bytes per
+    lane, each the best of three runs."""
+    import paper_1905_03213_amd as W
+
+    return {f"{w}B": max(W.measure_vmem(w, rounds=4096)[0] for _ in range(3)) for w in (4, 8, 16)}
 
 
 def measure_lds_peak():

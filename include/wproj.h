@@ -423,6 +423,20 @@ int wproj_gather_rows(int64_t n_rows, int64_t row_bytes, const int64_t *perm, in
  */
 int wproj_measure_lds(int mode, int32_t rounds, double *bytes_per_second, double *ms, void *stream);
 
+/*
+ * Measures the rate at which the vector-memory path returns data from L1 to the
+ * registers, for buffer loads of `width` bytes per lane (4, 8 or 16: the tap fetches of
+ * the gridder and degridder load 8 or 16 bytes per lane).  Every CU runs resident
+ * workgroups of 256 lanes that stream loads with 8 in flight per lane from a 16 KiB
+ * window that stays in L1; the kernel is timed with HIP events on `stream` after one
+ * warm-up launch (synchronous: the call waits for the timing).  bytes_per_second
+ * receives bytes delivered to registers / elapsed time (all CUs together); ms (nullable)
+ * the launch time.  rounds in [1, 2^20] sets the length of the launch.  Allocates and
+ * frees a 16 KiB window (zeroed) and a small output buffer.  Errors: WPROJ_EINVAL,
+ * WPROJ_ENOMEM, WPROJ_EHIP.
+ */
+int wproj_measure_vmem(int width, int32_t rounds, double *bytes_per_second, double *ms, void *stream);
+
 /* Message describing the last non-OK status returned on the calling thread ("" if none). */
 const char *wproj_last_error(void);
 

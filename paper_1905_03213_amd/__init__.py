@@ -27,6 +27,7 @@ from .wproj import (  # noqa: F401
     last_error,
     make_kernels,
     measure_lds,
+    measure_vmem,
     noalloc_scratch_bytes,
     regroup_channels,
     regroup_rows,

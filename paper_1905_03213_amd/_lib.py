@@ -25,7 +25,7 @@ EXPORTED = ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_w
             "wproj_footprints", "wproj_regroup_workspace_size", "wproj_regroup_rows",
             "wproj_gather_rows", "wproj_plan_create", "wproj_plan_free", "wproj_grid_planned",
             "wproj_degrid_planned", "wproj_grid_noalloc", "wproj_noalloc_scratch_bytes",
-            "wproj_check_weights", "wproj_measure_lds", "wproj_regroup_channels")
+            "wproj_check_weights", "wproj_measure_lds", "wproj_measure_vmem", "wproj_regroup_channels")
 PHASES = ("bin", "grid", "plain", "fft", "correct", "degrid", "reduce")
 
 
@@ -100,12 +100,13 @@ def lib():
     L.wproj_check_weights.argtypes = [vp, vp, vp]
     L.wproj_regroup_channels.argtypes = [i64, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp]
     L.wproj_measure_lds.argtypes = [i32, ctypes.c_int32, vp, vp, vp]
+    L.wproj_measure_vmem.argtypes = [i32, ctypes.c_int32, vp, vp, vp]
     for name in ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_grid",
                  "wproj_degrid", "wproj_image", "wproj_autotune", "wproj_tuning", "wproj_profile",
                  "wproj_profile_read", "wproj_version", "wproj_footprints", "wproj_regroup_rows",
                  "wproj_gather_rows", "wproj_plan_create", "wproj_plan_free", "wproj_grid_planned",
                  "wproj_degrid_planned", "wproj_grid_noalloc", "wproj_check_weights", "wproj_measure_lds",
-                 "wproj_regroup_channels"):
+                 "wproj_measure_vmem", "wproj_regroup_channels"):
         getattr(L, name).restype = i32
     _lib = L
     return L

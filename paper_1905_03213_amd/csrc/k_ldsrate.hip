@@ -1,5 +1,8 @@
-// LDS data-rate measurement: the denominator of the tile gridder's roofline.
+// Data-rate measurements on the device: LDS (the denominator of the tile gridder's
+// LDS roofline) and the vector-memory return path from L1 (the path the kernel-table
+// taps of the gridder and degridder take).
 //
+// LDS:
 // Every workgroup streams 64-bit accesses through its own LDS buffer with the access
 // shape of the gridder's private tiles: each lane of a wavefront touches its own 8-byte
 // word, the 64 words of one instruction are consecutive (no bank conflicts), and each
@@ -75,8 +78,99 @@ hipError_t launch_lds_rate(int mode, int n_cu, int rounds, float2 *sink, int64_t
   return hipGetLastError();
 }
 
+// Vector-memory return rate: every lane loads W bytes per instruction (buffer loads of
+// 4, 8 or 16 bytes, as the tap fetches are) from a 16 KiB window that stays in L1,
+// kChains loads in flight per lane; 64 consecutive lanes read consecutive words, and
+// the address moves by a runtime stride each round.  The dwords are folded with XOR so
+// that none is dead.  Bytes moved = blocks x threads x rounds x kChains x W.
+constexpr uint32_t kVmemWindow = 16384;
+
+template <int W>
+__global__ void __launch_bounds__(kRateThreads)
+    vmem_rate_kernel(const uint32_t *__restrict__ win, int rounds, uint32_t stride, uint32_t *__restrict__ sink) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc((void *)win, (short)0, (int)kVmemWindow, 0x00020000);
+  const int t = threadIdx.x;
+  const uint32_t wave = (uint32_t)(t >> 6), lane = (uint32_t)(t & 63);
+  uint32_t acc = 0, off = wave * 64u * (uint32_t)W * kChains;
+  for (int i = 0; i < rounds; ++i) {
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) {
+      const uint32_t a = (off + (uint32_t)c * 64u * (uint32_t)W + lane * (uint32_t)W) & (kVmemWindow - 1u);
+      if constexpr (W == 16) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, a, 0, 0);
+        acc ^= v[0] ^ v[1] ^ v[2] ^ v[3];
+      } else if constexpr (W == 8) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, a, 0, 0);
+        acc ^= v[0] ^ v[1];
+      } else {
+        acc ^= __builtin_amdgcn_raw_buffer_load_b32(r, a, 0, 0);
+      }
+    }
+    off += stride;
+  }
+  // the window holds zeros, so acc is 0 and nothing is stored; keeps every load live
+  if (acc == 0xdeadbeefu) sink[blockIdx.x * kRateThreads + t] = acc;
+}
+
+hipError_t launch_vmem_rate(int width, int n_cu, int rounds, const uint32_t *win, uint32_t *sink,
+                            int64_t *bytes, hipStream_t s) {
+  auto kern = width == 16 ? vmem_rate_kernel<16> : width == 8 ? vmem_rate_kernel<8> : vmem_rate_kernel<4>;
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kRateThreads, 0);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = (unsigned)(n_cu * std::min(std::max(per_cu, 1), 64));
+  *bytes = (int64_t)blocks * kRateThreads * rounds * kChains * width;
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(kRateThreads), 0, s, win, rounds, 3u * 64u * 16u, sink);
+  return hipGetLastError();
+}
+
 }  // namespace
 }  // namespace wproj
+
+extern "C" int wproj_measure_vmem(int width, int32_t rounds, double *bytes_per_second, double *ms,
+                                  void *stream) {
+  using namespace wproj;
+  if (width != 4 && width != 8 && width != 16) return set_error(WPROJ_EINVAL, "width must be 4, 8 or 16 bytes");
+  if (rounds < 1 || rounds > (1 << 20)) return set_error(WPROJ_EINVAL, "rounds must be in [1, 2^20]");
+  if (!bytes_per_second) return set_error(WPROJ_EINVAL, "bytes_per_second is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return set_error(WPROJ_EHIP, "device query failed");
+  const int n_cu = prop.multiProcessorCount;
+  uint32_t *win = nullptr, *sink = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  struct Guard {
+    uint32_t *&w, *&k;
+    hipEvent_t &a, &b;
+    ~Guard() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+      (void)hipFree(w);
+      (void)hipFree(k);
+    }
+  } guard{win, sink, e0, e1};
+  const size_t sink_bytes = (size_t)n_cu * 64 * kRateThreads * sizeof(uint32_t);
+  if (hipMalloc(&win, kVmemWindow) != hipSuccess || hipMalloc(&sink, sink_bytes) != hipSuccess)
+    return set_error(WPROJ_ENOMEM, "buffer allocation failed");
+  if (hipMemset(win, 0, kVmemWindow) != hipSuccess) return set_error(WPROJ_EHIP, "hipMemset failed");
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return set_error(WPROJ_EHIP, "hipEventCreate failed");
+  int64_t bytes = 0;
+  if (launch_vmem_rate(width, n_cu, rounds, win, sink, &bytes, s) != hipSuccess)  // warm-up
+    return set_error(WPROJ_EHIP, "vector-memory rate kernel launch failed");
+  if (hipEventRecord(e0, s) != hipSuccess || launch_vmem_rate(width, n_cu, rounds, win, sink, &bytes, s) != hipSuccess ||
+      hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+    return set_error(WPROJ_EHIP, "vector-memory rate measurement failed");
+  float t = 0.0f;
+  if (hipEventElapsedTime(&t, e0, e1) != hipSuccess || !(t > 0.0f))
+    return set_error(WPROJ_EHIP, "hipEventElapsedTime failed");
+  *bytes_per_second = (double)bytes / ((double)t * 1e-3);
+  if (ms) *ms = t;
+  return WPROJ_OK;
+}
 
 extern "C" int wproj_measure_lds(int mode, int32_t rounds, double *bytes_per_second, double *ms,
                                  void *stream) {

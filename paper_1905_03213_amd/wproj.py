@@ -191,6 +191,15 @@ def measure_lds(mode: int, rounds: int = 4096, stream=None) -> tuple:
     return bps.value, ms.value
 
 
+def measure_vmem(width: int, rounds: int = 4096, stream=None) -> tuple:
+    """wproj_measure_vmem: (bytes per second, kernel ms) of L1-resident buffer loads of
+    `width` (4, 8 or 16) bytes per lane."""
+    bps, ms = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _lib.check("wproj_measure_vmem", _lib.lib().wproj_measure_vmem(
+        int(width), int(rounds), ctypes.byref(bps), ctypes.byref(ms), _stream(stream)))
+    return bps.value, ms.value
+
+
 def grid_noalloc(k: Kernels, uvw: torch.Tensor, vis: torch.Tensor, weight: torch.Tensor,
                  grid_out: torch.Tensor, image_offsets: Optional[torch.Tensor] = None,
                  weight_sum: Optional[torch.Tensor] = None, counters: Optional[torch.Tensor] = None,

@@ -104,3 +104,17 @@ def test_regroup_and_gather_argument_checks():
     assert L.wproj_gather_rows(4, 0, fake, 4, fake, fake, None, None) == -1
     assert L.wproj_gather_rows(-1, 8, fake, 4, fake, fake, None, None) == -1
     assert L.wproj_gather_rows(4, 8, None, 4, fake, fake, None, None) == -1
+
+
+def test_rate_measurements_check_arguments():
+    L = _lib.lib()
+    bps = ctypes.c_double(0.0)
+    # invalid mode, width or rounds, or a NULL result, are refused before any GPU work
+    assert L.wproj_measure_lds(3, 16, ctypes.byref(bps), None, None) == -1
+    assert L.wproj_measure_lds(0, 0, ctypes.byref(bps), None, None) == -1
+    assert L.wproj_measure_lds(0, 16, None, None, None) == -1
+    assert L.wproj_measure_vmem(12, 16, ctypes.byref(bps), None, None) == -1
+    assert L.wproj_measure_vmem(16, (1 << 20) + 1, ctypes.byref(bps), None, None) == -1
+    assert L.wproj_measure_vmem(8, 16, None, None, None) == -1
+    assert L.wproj_measure_vmem(2, 16, ctypes.byref(bps), None, None) == -1
+    assert b"width" in L.wproj_last_error()

@@ -129,3 +129,31 @@ def test_tiled_degrid_fixed_supports(s_full):
     assert rel_max(got, ref) <= TOL["f32"]
     assert np.count_nonzero(got) == np.count_nonzero(ref)
     k.free()
+
+
+@pytest.mark.parametrize("s_full", [4, 7, 8])
+@pytest.mark.parametrize("tile,chunk", [(16, 256), (32, 300), (32, 8192), (64, 1000)])
+def test_tap_lane_degrid_tiles_and_chunks(s_full, tile, chunk):
+    """The one-tap-per-lane degridder (FP32 tables, fixed support up to 8) reads cells at
+    offsets set by the tile's row pitch, and a team of four wavefronts splits each work
+    item into batches of 64 records: tiles 16, 32 and 64, and work items of 256, 300, 1000
+    and 8192 records (ragged last batches, items shorter than one batch per wavefront)
+    against the oracle, with dense hot tiles so that items split."""
+    params = {**_fixed_params(s_full, "f32"), "tile": tile, "chunk": chunk}
+    rng = np.random.default_rng(11)
+    uvw, _, _ = _inputs(params, 12, nvis=30000)
+    # a third of the rows in a small hot region, so its tiles hold several work items
+    hot = rng.random(uvw.shape[0]) < 0.33
+    uvw[hot, :2] = rng.uniform(-15.0, 15.0, (int(hot.sum()), 2))
+    plan = R.Plan(params)
+    tabs = R.kernel_tables(plan)
+    n = plan.n
+    M = (rng.standard_normal((1, n, n)) + 1j * rng.standard_normal((1, n, n))).astype(np.complex64)
+    k = W.make_kernels(params)
+    out = torch.full((uvw.shape[0],), 7.0 + 7.0j, dtype=torch.complex64, device="cuda")
+    W.degrid(k, torch.as_tensor(uvw).cuda(), torch.as_tensor(M).cuda(), out)
+    ref = R.degrid(plan, tabs, uvw, M.astype(np.complex128))
+    got = out.to(torch.complex128).cpu().numpy()
+    assert rel_max(got, ref) <= TOL["f32"]
+    assert np.count_nonzero(got) == np.count_nonzero(ref)
+    k.free()
