@@ -329,7 +329,7 @@ def main():
                 run_accumulation(W, k, params, a1, a2, n_ant, n_ch, uvw, vis32, wt32, stream, reps))
         del perm, a1, a2
 
-    extra = {"phases_ms": per, "tuning": {"tile": tile, "chunk": chunk},
+    extra = {"phases_ms": per, "tuning": {"tile": tile, "chunk": chunk, "bin_aggregate": k.tuning_all()[2]},
              "graph_replay_ms_per_step": graph_ms,
              "counters": {"dropped": counters[0], "w_clamped": counters[1], "bad_weight": counters[2]},
              "nvis_total": nvis, "nvis_gridded": n_valid}
@@ -754,12 +754,13 @@ def time_config(name, dev, args, peak_lds):
                         f"{params['n_wplanes']} w-planes, supports {min(k.export(W._lib.EXPORT_SUPPORTS).view(torch.int32).tolist())}"
                         f"..{k.export(W._lib.EXPORT_SUPPORTS).view(torch.int32).max().item()}, {prec}"),
            "nvis": wl.nvis, "nvis_gridded": n_valid, "ms_per_step": ms, "mvis_per_s": n_valid / ms / 1e3,
-           "graph_replay_ms_per_step": graph_ms, "phases_ms": per, "tuning": {"tile": tile, "chunk": chunk},
+           "graph_replay_ms_per_step": graph_ms, "phases_ms": per,
+           "tuning": {"tile": tile, "chunk": chunk, "bin_aggregate": k.tuning_all()[2]},
            "mean_taps_per_vis": taps / max(n_valid, 1),
            "grid_kernel_lds_frac": lds_bytes / (per["grid"] * 1e-3) / peak_lds,
            "call_lds_frac": lds_bytes / (t_call * 1e-3) / peak_lds}
     log(f"{name}: {ms:.3f} ms/step, {n_valid / ms / 1e3:.1f} Mvis/s, phases {per}, "
-        f"generated in {time.time() - t0:.1f} s")
+        f"tuning {k.tuning_all()}, generated in {time.time() - t0:.1f} s")
     del ws, g, img
     k.free()
     return out

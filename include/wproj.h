@@ -120,6 +120,16 @@ typedef struct {
                                Grids then hold n_images L planes [image][layer][n][n]; the
                                image combines an image's layers (w-stacking, one of the
                                wide-field methods the paper's introduction lists, Section 1). */
+  int32_t bin_aggregate;    /* 0 or 1: how binning counts visibilities per bin (the same bins
+                               and results either way).  0: the first lane of each run of
+                               equal bins in a wavefront adds the run with one global atomic,
+                               which suits rows in measurement-set order (a row's channels
+                               share bins).  1: blocks of 4096 visibilities first add their
+                               counts in an LDS hash table, then take one global atomic per
+                               distinct bin, which suits rows whose equal bins lie hundreds of
+                               rows apart (one channel per row in time order: the same
+                               baseline recurs every few hundred rows, in the same bin for
+                               minutes).  wproj_autotune times both. */
   int32_t reserved[1];      /* must be zero */
 } wproj_params;
 
@@ -266,8 +276,9 @@ int wproj_check_weights(const wproj_kernels *k, const double *weight_sum, void *
  * Choose the tiled gridder's tile side (16, 32 or 64 cells, each where one wavefront's
  * tile copy with its halo fits in a workgroup's LDS) and work-item length (1024 ..
  * 16384 binned records) for this handle by timing each candidate on the caller's data
- * (one warm-up and one timed wproj_grid per candidate, HIP events on `stream`), then keep
- * the fastest in the handle.  The choice is also cached per problem shape (grid size,
+ * (one warm-up and one timed wproj_grid per candidate, HIP events on `stream`), then, at
+ * the fastest of those, binning with counts aggregated per block (bin_aggregate = 1)
+ * against per-wavefront runs (0), and keep the fastest configuration in the handle.  The choice is also cached per problem shape (grid size,
  * images, planes, supports, oversampling, precision, visibility count rounded to a
  * power of two) for the life of the process, and later calls on a handle of the same
  * shape reuse it without timing.  Arguments are those of wproj_grid; scratch_grid
@@ -283,8 +294,9 @@ int wproj_autotune(wproj_kernels *k, int64_t nvis, const double *uvw, const void
                    const void *weight, const int64_t *image_offsets, void *scratch_grid,
                    void *workspace, int64_t workspace_bytes, void *stream);
 
-/* The tiled gridder configuration in use: *tile (cells) and *chunk (records), host. */
-int wproj_tuning(const wproj_kernels *k, int32_t *tile, int32_t *chunk);
+/* The tiled gridder configuration in use: *tile (cells), *chunk (records) and
+ * *bin_aggregate (wproj_params::bin_aggregate); host pointers, each nullable. */
+int wproj_tuning(const wproj_kernels *k, int32_t *tile, int32_t *chunk, int32_t *bin_aggregate);
 
 /* Phases timed by wproj_profile. */
 typedef enum {

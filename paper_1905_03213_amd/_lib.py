@@ -47,6 +47,7 @@ class Params(ctypes.Structure):
         ("w_mode", ctypes.c_int32),
         ("accumulate_runs", ctypes.c_int32),
         ("n_wlayers", ctypes.c_int32),
+        ("bin_aggregate", ctypes.c_int32),
         ("reserved", ctypes.c_int32 * 1),
     ]
 
@@ -79,7 +80,8 @@ def lib():
     L.wproj_degrid.argtypes = [vp, i64, vp, vp, vp, vp, vp, i64, vp]
     L.wproj_image.argtypes = [vp, i32, vp, vp, vp, vp, i64, vp]
     L.wproj_autotune.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, i64, vp]
-    L.wproj_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    L.wproj_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_int32)]
     L.wproj_profile.argtypes = [vp, i32]
     L.wproj_profile_read.argtypes = [vp, vp, vp]
     L.wproj_last_error.restype = ctypes.c_char_p

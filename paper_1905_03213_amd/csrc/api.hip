@@ -149,6 +149,8 @@ int validate(const wproj_params *p, std::vector<int32_t> &supp) {
   }
   if (p->accumulate_runs != 0 && p->accumulate_runs != 1)
     return fail(WPROJ_EINVAL, "accumulate_runs must be 0 or 1");
+  if (p->bin_aggregate != 0 && p->bin_aggregate != 1)
+    return fail(WPROJ_EINVAL, "bin_aggregate must be 0 or 1");
   for (int r : p->reserved)
     if (r != 0) return fail(WPROJ_EINVAL, "reserved fields must be zero");
   supp.assign(p->n_wplanes, p->support);
@@ -222,6 +224,7 @@ BinShape bin_shape(const wproj_kernels *k) {
   B.nty = B.ntx;
   B.kw = k->plane_in_key ? k->params.n_wplanes : 1;
   B.chunk = k->chunk;
+  B.aggregate = k->bin_aggregate;
   // a fixed support with a kernel of its own, and sub-kernel numbers that fit above the
   // LDS offset
   const int64_t n_sub = (int64_t)k->params.n_wplanes * k->params.oversample * k->params.oversample;
@@ -317,7 +320,10 @@ struct TuneKey {
   }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+struct TuneChoice {
+  int tile, chunk, bin_aggregate;
+};
+std::map<TuneKey, TuneChoice> g_tune_cache;
 
 }  // namespace
 
@@ -421,6 +427,7 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
     k->tile = 16;
   }
   if (params->chunk) k->chunk = params->chunk;
+  k->bin_aggregate = params->bin_aggregate;
 
   Geometry &G = k->geo;
   G.n = n;
@@ -621,11 +628,12 @@ int wproj_grid(const wproj_kernels *k, int64_t nvis, const double *uvw, const vo
   return WPROJ_OK;
 }
 
-int wproj_tuning(const wproj_kernels *k, int32_t *tile, int32_t *chunk) {
+int wproj_tuning(const wproj_kernels *k, int32_t *tile, int32_t *chunk, int32_t *bin_aggregate) {
   g_err.clear();
   if (!k) return fail(WPROJ_EINVAL, "handle is NULL");
   if (tile) *tile = k->tile;
   if (chunk) *chunk = k->chunk;
+  if (bin_aggregate) *bin_aggregate = k->bin_aggregate;
   return WPROJ_OK;
 }
 
@@ -645,8 +653,9 @@ int wproj_autotune(wproj_kernels *k, int64_t nvis, const double *uvw, const void
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      k->tile = it->second.first;
-      k->chunk = it->second.second;
+      k->tile = it->second.tile;
+      k->chunk = it->second.chunk;
+      k->bin_aggregate = it->second.bin_aggregate;
       k->plane_in_key = plane_in_key_for(k, k->tile);
       return WPROJ_OK;
     }
@@ -664,46 +673,59 @@ int wproj_autotune(wproj_kernels *k, int64_t nvis, const double *uvw, const void
   } eg{e0, e1};
   const bool was_profiling = k->profiling;
   k->profiling = false;
-  const int tile0 = k->tile, chunk0 = k->chunk;
+  const TuneChoice start{k->tile, k->chunk, k->bin_aggregate};
+  auto set = [&](const TuneChoice &c) {
+    k->tile = c.tile;
+    k->chunk = c.chunk;
+    k->bin_aggregate = c.bin_aggregate;
+    k->plane_in_key = plane_in_key_for(k, c.tile);
+  };
+  // one warm-up and one timed call of a candidate; on failure the handle is restored
+  auto time_one = [&](const TuneChoice &c, float &ms) -> int {
+    set(c);
+    int rc = wproj_grid(k, nvis, uvw, vis, weight, image_offsets, scratch_grid, nullptr, nullptr,
+                        workspace, workspace_bytes, stream);
+    if (rc == WPROJ_OK) {
+      if (hipEventRecord(e0, s) != hipSuccess) rc = fail(WPROJ_EHIP, "hipEventRecord failed");
+      if (rc == WPROJ_OK)
+        rc = wproj_grid(k, nvis, uvw, vis, weight, image_offsets, scratch_grid, nullptr, nullptr,
+                        workspace, workspace_bytes, stream);
+      if (rc == WPROJ_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(WPROJ_EHIP, "event timing failed");
+    }
+    if (rc != WPROJ_OK) {
+      set(start);
+      k->profiling = was_profiling;
+    }
+    return rc;
+  };
+  // tile and work-item length with per-wavefront counting, then the block-aggregated
+  // counting at the best of those
   float best = -1.0f;
-  int best_tile = tile0, best_chunk = chunk0;
+  TuneChoice pick = start;
   for (int tile : kTuneTiles) {
     if (tile_shape(k, tile).lds_bytes + 256 > k->max_lds) continue;
     for (int chunk : kTuneChunks) {
-      k->tile = tile;
-      k->chunk = chunk;
-      k->plane_in_key = plane_in_key_for(k, tile);
-      int rc = wproj_grid(k, nvis, uvw, vis, weight, image_offsets, scratch_grid, nullptr, nullptr,
-                          workspace, workspace_bytes, stream);
-      if (rc == WPROJ_OK) {
-        HIP_TRY(hipEventRecord(e0, s));
-        rc = wproj_grid(k, nvis, uvw, vis, weight, image_offsets, scratch_grid, nullptr, nullptr,
-                        workspace, workspace_bytes, stream);
-        HIP_TRY(hipEventRecord(e1, s));
-      }
-      if (rc != WPROJ_OK) {
-        k->tile = tile0;
-        k->chunk = chunk0;
-        k->plane_in_key = plane_in_key_for(k, tile0);
-        k->profiling = was_profiling;
-        return rc;
-      }
-      HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.0f;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      const int rc = time_one({tile, chunk, 0}, ms);
+      if (rc != WPROJ_OK) return rc;
       if (best < 0.0f || ms < best) {
         best = ms;
-        best_tile = tile;
-        best_chunk = chunk;
+        pick = {tile, chunk, 0};
       }
     }
   }
-  k->tile = best_tile;
-  k->chunk = best_chunk;
-  k->plane_in_key = plane_in_key_for(k, best_tile);
+  {
+    float ms = 0.0f;
+    const int rc = time_one({pick.tile, pick.chunk, 1}, ms);
+    if (rc != WPROJ_OK) return rc;
+    if (ms < best) pick.bin_aggregate = 1;
+  }
+  set(pick);
   k->profiling = was_profiling;
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune_cache[key] = {best_tile, best_chunk};
+  g_tune_cache[key] = pick;
   return WPROJ_OK;
 }
 

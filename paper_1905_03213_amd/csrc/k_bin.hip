@@ -227,6 +227,180 @@ __global__ void __launch_bounds__(kBinBlock)
   }
 }
 
+// The key pass with counts aggregated per block in an LDS hash table: a block of
+// kAggThreads threads takes kAggSpan consecutive visibilities, the first lane of each
+// run of equal keys adds the run to its key's entry (slot within the block's share of
+// the key = the returned count), and one global count atomic per distinct key of the
+// block then reserves the block's share (its base).  Where the same keys recur within a
+// few thousand rows (rows in time order, one channel each: the same baseline every few
+// hundred rows, in the same tile and plane for minutes), this replaces most global
+// atomics by LDS atomics; where equal keys are adjacent (a row's channels, measurement-
+// set order) the wavefront runs already do that and the table only costs time, so the
+// choice is the handle's (BinShape::aggregate, which wproj_autotune times).  A run whose
+// key finds no entry within kAggProbes probes takes a global atomic of its own.  Same
+// outputs as key_kernel.
+constexpr int kAggThreads = 1024;
+constexpr int kAggVpt = 4;
+constexpr int kAggSpan = kAggThreads * kAggVpt;
+constexpr int kAggSlots = 4096;  // a power of two
+constexpr int kAggProbes = 16;
+constexpr uint32_t kDirect = 0xffffffffu;  // entry index of a run counted globally
+
+__device__ inline uint32_t agg_hash(uint32_t key) { return (key * 2654435761u) >> (32 - 12); }
+static_assert(kAggSlots == 1 << 12, "agg_hash yields 12 bits");
+
+template <typename Real, bool COMPACT>
+__global__ void __launch_bounds__(kAggThreads)
+    key_agg_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
+                   const Real *__restrict__ wt, const int64_t *__restrict__ img_off,
+                   int S_fix, uint32_t *__restrict__ slots, uint32_t *count, double *wsum,
+                   unsigned long long *counters) {
+  constexpr int V = kAggVpt;
+  __shared__ uint32_t h_key[kAggSlots], h_cnt[kAggSlots], h_base[kAggSlots];
+  for (int i = threadIdx.x; i < kAggSlots; i += kAggThreads) {
+    h_key[i] = kInvalid;
+    h_cnt[i] = 0;
+  }
+  const int64_t j_first = (int64_t)blockIdx.x * kAggSpan;
+  auto row = [&](int i) { return j_first + i * kAggThreads + threadIdx.x; };
+  // every load of the thread first
+  double c[V][3];
+  Real wj[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const int64_t j = row(i);
+    c[i][0] = c[i][1] = c[i][2] = 0.0;
+    wj[i] = Real(0);
+    if (j < nvis) {
+      c[i][0] = uvw[3 * j];
+      c[i][1] = uvw[3 * j + 1];
+      c[i][2] = uvw[3 * j + 2];
+      wj[i] = wt ? wt[j] : Real(1);
+    }
+  }
+  // image of the block's first row, and of all its rows when one image holds them
+  int img_b = -1, img_all = -1;
+  if (j_first < nvis) {
+    img_b = image_of(img_off, G.n_images, j_first);
+    const int last = image_of(img_off, G.n_images, min(j_first + (int64_t)kAggSpan, nvis) - 1);
+    img_all = img_b >= 0 && img_b == last ? img_b : -1;
+  }
+  uint32_t key[V], packed[V];
+  bool fold[V];
+  double w_mine = 0.0;
+  unsigned n_drop = 0, n_clamp = 0, n_bad = 0;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const int64_t j = row(i);
+    key[i] = kInvalid;
+    packed[i] = 0;
+    fold[i] = false;
+    int cls = kFlagged;
+    bool clamped = false;
+    if (j < nvis) {
+      const int img = img_all >= 0 ? img_all : image_of(img_off, G.n_images, j);
+      if (img >= 0) {
+        Footprint f;
+        cls = classify(G, c[i], wj[i], f, COMPACT ? S_fix : 0);
+        if (cls == kGridded) {
+          key[i] = bin_key(G, B, img, f);
+          fold[i] = f.fold;
+          if constexpr (COMPACT) packed[i] = record_lds(G, B, f);
+          clamped = w_clamped(G, c[i][2]);
+          if (img == img_b)
+            w_mine += (double)wj[i];
+          else if (wsum)
+            unsafeAtomicAdd(&wsum[(int64_t)img * kSlots + (blockIdx.x & (kSlots - 1))], (double)wj[i]);
+        }
+      }
+    }
+    n_drop += (unsigned)__popcll(__ballot(cls == kDropped));
+    n_bad += (unsigned)__popcll(__ballot(cls == kBadWeight));
+    n_clamp += (unsigned)__popcll(__ballot(clamped));
+  }
+  __syncthreads();  // the table is cleared
+  // runs into the table: entry and rank of each run's first lane
+  Run run[V];
+  uint32_t where[V], rank[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    run[i] = run_of(key[i]);
+    uint32_t e = kDirect, r = 0;
+    if (run[i].lead) {
+      uint32_t h = agg_hash(key[i]);
+      for (int probe = 0; probe < kAggProbes; ++probe) {
+        const uint32_t old = atomicCAS(&h_key[h], kInvalid, key[i]);
+        if (old == kInvalid || old == key[i]) {
+          e = h;
+          break;
+        }
+        h = (h + 1u) & (uint32_t)(kAggSlots - 1);
+      }
+      r = e == kDirect ? atomicAdd(&count[key[i]], run[i].len) : atomicAdd(&h_cnt[e], run[i].len);
+    }
+    where[i] = e;
+    rank[i] = r;
+  }
+  __syncthreads();  // every run is in the table
+  // one global atomic per distinct key of the block
+  uint32_t gb[kAggSlots / kAggThreads];
+#pragma unroll
+  for (int q = 0; q < kAggSlots / kAggThreads; ++q) {
+    const int e = threadIdx.x + q * kAggThreads;
+    const uint32_t k = h_key[e];
+    uint32_t b = 0;
+    if (k != kInvalid) b = atomicAdd(&count[k], h_cnt[e]);
+    gb[q] = b;
+  }
+#pragma unroll
+  for (int q = 0; q < kAggSlots / kAggThreads; ++q) h_base[threadIdx.x + q * kAggThreads] = gb[q];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const int64_t j = row(i);
+    const uint32_t e = (uint32_t)__shfl((int)where[i], run[i].leader, 64);
+    const uint32_t r = (uint32_t)__shfl((int)rank[i], run[i].leader, 64);
+    const uint32_t slot = (e == kDirect ? r : h_base[e & (uint32_t)(kAggSlots - 1)] + r) +
+                          (uint32_t)((threadIdx.x & 63) - run[i].leader);
+    if (j < nvis) {
+      slots[j] = slot;
+      if constexpr (COMPACT) {
+        slots[nvis + j] = fold[i] ? (key[i] | kFoldBit) : key[i];
+        slots[2 * nvis + j] = packed[i];
+      }
+    }
+  }
+  // counters and weight sums, as in key_kernel
+  __shared__ double s_w[kAggThreads / 64];
+  __shared__ unsigned s_c[3][kAggThreads / 64];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int acc_slot = blockIdx.x & (kSlots - 1);
+  const double wv = wave_sum(w_mine);
+  if (lane == 0) {
+    s_w[wid] = wv;
+    s_c[0][wid] = n_drop;
+    s_c[1][wid] = n_clamp;
+    s_c[2][wid] = n_bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tw = 0.0;
+    unsigned c0 = 0, c1 = 0, c2 = 0;
+    for (int i = 0; i < kAggThreads / 64; ++i) {
+      tw += s_w[i];
+      c0 += s_c[0][i];
+      c1 += s_c[1][i];
+      c2 += s_c[2][i];
+    }
+    if (wsum && img_b >= 0 && tw != 0.0) unsafeAtomicAdd(&wsum[(int64_t)img_b * kSlots + acc_slot], tw);
+    if (counters) {
+      if (c0) atomicAdd(&counters[0 * kSlots + acc_slot], (unsigned long long)c0);
+      if (c1) atomicAdd(&counters[1 * kSlots + acc_slot], (unsigned long long)c1);
+      if (c2) atomicAdd(&counters[2 * kSlots + acc_slot], (unsigned long long)c2);
+    }
+  }
+}
+
 // COMPACT: the key pass stored each visibility's key and packed first word (fixed
 // support S_fix, whose sub-kernel number n starts at tap n S_fix^2); otherwise the
 // footprint is computed again from the same inputs, with the same outcome.  A
@@ -478,22 +652,40 @@ hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, c
   double *wpart = wsum ? W.wslots : nullptr;
   auto *cnt = counters ? W.cslots : nullptr;
   const dim3 key_grid(nblk(nvis, kBinBlock * kKeyVpt)), grid(nblk(nvis, kBinBlock)), block(kBinBlock);
+  const bool agg = B.aggregate != 0;  // counts aggregated per block in LDS
+  const dim3 agg_grid(nblk(nvis, kAggSpan)), agg_block(kAggThreads);
   const bool compact = B.pack_sub != 0;
   const int S_fix = k->s_max;  // the fixed support of packed records
   if (k->params.precision == WPROJ_F64) {
     if (compact)
-      hipLaunchKernelGGL((key_kernel<double, true>), key_grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
-                         img_off, S_fix, W.slots, W.count, wpart, cnt);
+      if (agg)
+        hipLaunchKernelGGL((key_agg_kernel<double, true>), agg_grid, agg_block, 0, s, G, B, nvis, uvw,
+                           (const double *)wt, img_off, S_fix, W.slots, W.count, wpart, cnt);
+      else
+        hipLaunchKernelGGL((key_kernel<double, true>), key_grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
+                           img_off, S_fix, W.slots, W.count, wpart, cnt);
     else
-      hipLaunchKernelGGL((key_kernel<double, false>), key_grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
-                         img_off, S_fix, W.slots, W.count, wpart, cnt);
+      if (agg)
+        hipLaunchKernelGGL((key_agg_kernel<double, false>), agg_grid, agg_block, 0, s, G, B, nvis, uvw,
+                           (const double *)wt, img_off, S_fix, W.slots, W.count, wpart, cnt);
+      else
+        hipLaunchKernelGGL((key_kernel<double, false>), key_grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
+                           img_off, S_fix, W.slots, W.count, wpart, cnt);
   } else {
     if (compact)
-      hipLaunchKernelGGL((key_kernel<float, true>), key_grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
-                         img_off, S_fix, W.slots, W.count, wpart, cnt);
+      if (agg)
+        hipLaunchKernelGGL((key_agg_kernel<float, true>), agg_grid, agg_block, 0, s, G, B, nvis, uvw,
+                           (const float *)wt, img_off, S_fix, W.slots, W.count, wpart, cnt);
+      else
+        hipLaunchKernelGGL((key_kernel<float, true>), key_grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
+                           img_off, S_fix, W.slots, W.count, wpart, cnt);
     else
-      hipLaunchKernelGGL((key_kernel<float, false>), key_grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
-                         img_off, S_fix, W.slots, W.count, wpart, cnt);
+      if (agg)
+        hipLaunchKernelGGL((key_agg_kernel<float, false>), agg_grid, agg_block, 0, s, G, B, nvis, uvw,
+                           (const float *)wt, img_off, S_fix, W.slots, W.count, wpart, cnt);
+      else
+        hipLaunchKernelGGL((key_kernel<float, false>), key_grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
+                           img_off, S_fix, W.slots, W.count, wpart, cnt);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (wsum || counters) {

@@ -139,6 +139,7 @@ struct BinShape {
   int kw;
   int chunk;         // max records per work item
   int pack_sub;      // records carry the sub-kernel number in Record::lds (fixed support)
+  int aggregate;     // the key pass aggregates counts per block in LDS (wproj_params::bin_aggregate)
   int64_t n_tiles;   // n_images * ntx * nty
   int64_t n_keys;    // n_tiles * kw
 };

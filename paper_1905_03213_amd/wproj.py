@@ -99,9 +99,14 @@ class Kernels:
 
     def tuning(self) -> tuple:
         """wproj_tuning: (tile, chunk) of the tiled gridder."""
-        t, c = ctypes.c_int32(0), ctypes.c_int32(0)
-        _lib.check("wproj_tuning", _lib.lib().wproj_tuning(self.handle, ctypes.byref(t), ctypes.byref(c)))
-        return int(t.value), int(c.value)
+        return self.tuning_all()[:2]
+
+    def tuning_all(self) -> tuple:
+        """wproj_tuning: (tile, chunk, bin_aggregate)."""
+        t, c, a = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        _lib.check("wproj_tuning", _lib.lib().wproj_tuning(self.handle, ctypes.byref(t), ctypes.byref(c),
+                                                           ctypes.byref(a)))
+        return int(t.value), int(c.value), int(a.value)
 
     def new_grid(self, device="cuda") -> torch.Tensor:
         return torch.zeros((self.n_grids, self.params["n"], self.params["n"]), dtype=self.cplx,
@@ -120,7 +125,7 @@ def make_kernels(params: dict, stream=None) -> Kernels:
     support_per_plane (list or None), oversample, kernel_image_size, precision
     ("f64" | "f32" | "f32_f16table"), n_images, algorithm ("tiled" | "plain"), tile, chunk,
     w_mode ("linear" | "fold" | "fold_sqrt" | "stack"), n_wlayers (w-stacking layers),
-    accumulate_runs (bool)."""
+    accumulate_runs (bool), bin_aggregate (bool)."""
     P = _lib.Params()
     P.n = int(params["n"])
     P.n_wplanes = int(params["n_wplanes"])
@@ -145,6 +150,7 @@ def make_kernels(params: dict, stream=None) -> Kernels:
     P.w_mode = _WMODE[wm] if isinstance(wm, str) else int(wm)
     P.n_wlayers = int(params.get("n_wlayers", 0) or 0)
     P.accumulate_runs = int(bool(params.get("accumulate_runs", False)))
+    P.bin_aggregate = int(bool(params.get("bin_aggregate", False)))
     h = ctypes.c_void_p()
     _lib.check("wproj_make_kernels",
                _lib.lib().wproj_make_kernels(ctypes.byref(P), _stream(stream), ctypes.byref(h)))

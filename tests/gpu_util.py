@@ -71,8 +71,8 @@ def planted(wl, seed=0, n_bad=7):
     """Copies of a workload's arrays with random weights and planted special rows:
     zero weights, a negative and a NaN weight, non-finite uvw, an off-grid row."""
     rng = np.random.default_rng(seed)
-    uvw = np.array(wl.uvw, dtype=np.float64, copy=True)
-    vis = np.array(wl.vis, dtype=np.complex128, copy=True)
+    uvw = np.asarray(wl.uvw).astype(np.float64, copy=True)  # numpy or CPU tensor
+    vis = np.asarray(wl.vis).astype(np.complex128, copy=True)
     wt = rng.uniform(0.25, 2.0, uvw.shape[0])
     idx = rng.choice(uvw.shape[0], n_bad, replace=False)
     wt[idx[0]] = 0.0

@@ -43,6 +43,7 @@ def _params(**kw):
                                  dict(kernel_image_size=31), dict(precision=7), dict(n_images=0),
                                  dict(algorithm=5), dict(tile=48), dict(chunk=100),
                                  dict(w_mode=4), dict(w_mode=-1), dict(accumulate_runs=2),
+                                 dict(bin_aggregate=2), dict(bin_aggregate=-1),
                                  dict(n_wlayers=2), dict(w_mode=3, n_wlayers=-1),
                                  dict(w_mode=3, n_wlayers=4097)])
 def test_make_kernels_rejects_invalid_params(bad):
