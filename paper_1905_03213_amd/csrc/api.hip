@@ -452,11 +452,14 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
 
   if (hipMalloc(&k->d_supp, sizeof(int32_t) * n_w) != hipSuccess ||
       hipMalloc(&k->d_tab_off, sizeof(int64_t) * (n_w + 1)) != hipSuccess ||
-      hipMalloc(&k->d_tab, (size_t)k->n_taps * k->tap_bytes) != hipSuccess ||
+      hipMalloc(&k->d_tab, (size_t)(k->n_taps + kTabPad) * k->tap_bytes) != hipSuccess ||
       hipMalloc(&k->d_kappa, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&k->d_taper, sizeof(double) * m) != hipSuccess)
     return fail(WPROJ_ENOMEM, "device allocation of kernel tables (%lld taps) failed",
                 (long long)k->n_taps);
+  // the padding past the last sub-kernel is read (never used) by whole-wavefront tap loads
+  HIP_TRY(hipMemsetAsync((char *)k->d_tab + (size_t)k->n_taps * k->tap_bytes, 0,
+                         (size_t)kTabPad * k->tap_bytes, s));
   G.supp = k->d_supp;
   G.tab_off = k->d_tab_off;
   HIP_TRY(hipMemcpyAsync(k->d_supp, supp.data(), sizeof(int32_t) * n_w, hipMemcpyHostToDevice, s));

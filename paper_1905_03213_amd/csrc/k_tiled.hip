@@ -64,6 +64,31 @@ template <> struct Cx<double> { using T = double2; };
 // loads are all issued before the first is consumed, so up to kGroup memory latencies
 // overlap per wave.
 constexpr int kGroup = 8;
+
+// One tap of an FP32 or FP16 table loaded through a buffer resource (lane's byte offset
+// in the vector offset, the sub-kernel's in the scalar offset), kept raw until use.
+template <typename Tab> struct TapRaw;
+template <> struct TapRaw<float2> {
+  typedef uint32_t T __attribute__((ext_vector_type(2)));
+  __device__ static T load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  }
+  __device__ static float2 value(const T &v) { return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1])); }
+};
+template <> struct TapRaw<half2c> {
+  typedef uint32_t T;
+  __device__ static T load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+  }
+  __device__ static float2 value(const T &v) {
+    half2c h;
+    __builtin_memcpy(&h, &v, 4);
+    return make_float2((float)h.re, (float)h.im);
+  }
+};
+template <> struct TapRaw<double2> {  // the per-record-support fast path is FP32 only
+  typedef double2 T;
+};
 constexpr int kMaxWavesPerBlock = 4;
 
 // A row-carrying record (weight, row) turned into W V from the visibility it names; a
@@ -316,9 +341,86 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         }
         if (more) cur = nxt;
       }
+    } else if constexpr (kHasTap<Rec> && std::is_same_v<Real, float>) {
+      // Per-record supports with FP32 arithmetic.  Records arrive 64 at a time (one
+      // coalesced load, readlane broadcasts).  A record with S <= 8 takes one pass, lane t
+      // tap t; its taps load one group of kGroup records ahead, at a wave-uniform scalar
+      // offset (the table carries 64 zero taps past its end, so lanes t >= S^2 of its last
+      // sub-kernel stay inside it).  The lane's cell offset follows the support and is
+      // recomputed only when the support changes (a tile's records come plane by plane).
+      // Larger supports take their passes as they go.
+      using Raw = typename TapRaw<Tab>::T;
+      int s_cur = 0, p_off = 0;
+      bool p_on = false;
+      auto set_support = [&](int Sn) {
+        // t / Sn by a float reciprocal: (t + 1/2) / Sn lies at least 1/(2 Sn) from an
+        // integer, far beyond the rounding of this product
+        const int kv = (int)(((float)lane + 0.5f) * (1.0f / (float)Sn));
+        p_on = lane < Sn * Sn;
+        p_off = kv * pitch + (lane - kv * Sn);
+        s_cur = Sn;
+      };
+      const uint32_t vlane = (uint32_t)lane * (uint32_t)sizeof(Tab);
+      auto fetch_group = [&](const Rec &batch, int g, Raw (&dst)[kGroup]) {
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+          const uint32_t tp = bcast(batch.tap, g * kGroup + i);
+          if ((tp >> kTapBits) < 8u) dst[i] = TapRaw<Tab>::load(tab_rsrc, vlane, (tp & kTapMask) * (uint32_t)sizeof(Tab));
+        }
+      };
+      auto accumulate_group = [&](const Rec &batch, int g, const Raw (&src)[kGroup]) {
+        bool large = false;
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+          const int j = g * kGroup + i;
+          const uint32_t tp = bcast(batch.tap, j);
+          const int Sr = (int)(tp >> kTapBits) + 1;
+          if (Sr <= 8) {
+            if (Sr != s_cur) set_support(Sr);
+            const int base = (int)(bcast(batch.lds, j) & kLdsMask);
+            const Real rwr = bcast(batch.wr, j), rwi = bcast(batch.wi, j);
+            if (p_on) accumulate(acc, base + p_off, rwr, rwi, TapRaw<Tab>::value(src[i]));
+          } else {
+            large = true;
+          }
+        }
+        // records with S > 8 (several passes), their taps loaded as they go
+        if (large) {
+#pragma unroll 1
+          for (int i = 0; i < kGroup; ++i) {
+            const int j = g * kGroup + i;
+            const uint32_t tp = bcast(batch.tap, j);
+            const int Sr = (int)(tp >> kTapBits) + 1;
+            if (Sr <= 8) continue;
+            const uint32_t tb = tp & kTapMask;
+            const int base = (int)(bcast(batch.lds, j) & kLdsMask);
+            const Real rwr = bcast(batch.wr, j), rwi = bcast(batch.wi, j);
+            for (int t = lane; t < Sr * Sr; t += 64) {
+              const int kv = t / Sr, ku = t - kv * Sr;
+              accumulate(acc, base + kv * pitch + ku, rwr, rwi, tab_load(tab, tb + (uint32_t)t));
+            }
+          }
+        }
+      };
+      Rec cur;
+      load_batch(0, cur);
+      for (uint32_t b = 0; b < n_rec; b += 64) {
+        Rec nxt;
+        const bool more = b + 64 < n_rec;
+        if (more) load_batch(b + 64, nxt);
+        Raw c0[kGroup], c1[kGroup];
+        fetch_group(cur, 0, c0);
+        for (int g = 0; g < 64 / kGroup; g += 2) {
+          fetch_group(cur, g + 1, c1);
+          accumulate_group(cur, g, c0);
+          if (g + 2 < 64 / kGroup) fetch_group(cur, g + 2, c0);
+          accumulate_group(cur, g + 1, c1);
+        }
+        if (more) cur = nxt;
+      }
     } else if constexpr (kHasTap<Rec>) {
-      // General path (per-record support up to 32): records by wave-uniform loads, each
-      // record's taps in passes of 64 lanes.
+      // General path (FP64; per-record support up to 32): records by wave-uniform loads,
+      // each record's taps in passes of 64 lanes.
       for (uint32_t r = w.begin; r < w.end; ++r) {
         Rec rr = rec[r];
         if constexpr (PLANNED) to_weighted(rr, vis);

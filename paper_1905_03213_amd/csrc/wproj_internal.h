@@ -20,6 +20,10 @@ struct alignas(4) half2c {
 };
 
 // Geometry every kernel needs, passed by value.
+// Zero taps allocated past the end of a kernel table: a wavefront loading one sub-kernel
+// of up to 64 taps with lane t at tap t stays inside the allocation for the last one.
+constexpr int64_t kTabPad = 64;
+
 struct Geometry {
   int32_t n;        // grid side
   int32_t O;        // oversampling
