@@ -10,49 +10,60 @@
 // (-1)^(kx+ky) kappa kappa I at the shifted position, then an in-place forward FFT.
 // With w-stacking an image has one grid per layer: the grid -> image pass combines the
 // layers' transforms with their phase factors, and image -> grid writes every layer.
+#include <algorithm>
+
 #include "wproj_internal.h"
 
 namespace wproj {
 namespace {
 
+// Launch shape of the per-pixel kernels: blockIdx.x * 256 + threadIdx.x is the column,
+// blockIdx.y the row, and blockIdx.z steps through the images (or grids) by gridDim.z;
+// no per-element integer division.
+constexpr int kPixThreads = 256;
+constexpr unsigned kMaxGridZ = 65535;
+
 template <typename Real>
-__global__ void g2i_kernel(int n, int n_images, const Real *__restrict__ F,
-                           const double *__restrict__ kappa, const double *__restrict__ wsum,
-                           Real *__restrict__ img) {
+__global__ void __launch_bounds__(kPixThreads)
+    g2i_kernel(int n, int n_images, const Real *__restrict__ F, const double *__restrict__ kappa,
+               const double *__restrict__ wsum, Real *__restrict__ img) {
+  const int x = (int)(blockIdx.x * kPixThreads + threadIdx.x), y = (int)blockIdx.y;
+  if (x >= n) return;
   const int64_t cells = (int64_t)n * n;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cells * n_images) return;
-  const int i = (int)(t / cells);
-  const int64_t r = t - (int64_t)i * cells;
-  const int y = (int)(r / n), x = (int)(r - (int64_t)y * n);
   const int h = n / 2;
   const int ys = y + h < n ? y + h : y - h;
   const int xs = x + h < n ? x + h : x - h;
-  const double re = (double)F[2 * (cells * i + (int64_t)ys * n + xs)];
-  double scale = kappa[x] * kappa[y];
-  if (wsum != nullptr) {
-    const double s = wsum[i];
-    scale = s != 0.0 ? scale / s : 0.0;
+  const double kk = kappa[x] * kappa[y];
+  for (int i = (int)blockIdx.z; i < n_images; i += (int)gridDim.z) {
+    const double re = (double)F[2 * (cells * i + (int64_t)ys * n + xs)];
+    double scale = kk;
+    if (wsum != nullptr) {
+      const double s = wsum[i];
+      scale = s != 0.0 ? scale / s : 0.0;
+    }
+    const double v = ((x + y) & 1) ? -re : re;
+    img[cells * i + (int64_t)y * n + x] = (Real)(v * scale);
   }
-  const double v = ((x + y) & 1) ? -re : re;
-  img[t] = (Real)(v * scale);
 }
 
 template <typename Real>
-__global__ void i2g_kernel(int n, int n_images, const Real *__restrict__ img,
-                           const double *__restrict__ kappa, Real *__restrict__ G) {
+__global__ void __launch_bounds__(kPixThreads)
+    i2g_kernel(int n, int n_images, const Real *__restrict__ img, const double *__restrict__ kappa,
+               Real *__restrict__ G) {
+  const int kx = (int)(blockIdx.x * kPixThreads + threadIdx.x), ky = (int)blockIdx.y;
+  if (kx >= n) return;
   const int64_t cells = (int64_t)n * n;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cells * n_images) return;
-  const int i = (int)(t / cells);
-  const int64_t r = t - (int64_t)i * cells;
-  const int ky = (int)(r / n), kx = (int)(r - (int64_t)ky * n);
   const int h = n / 2;
   const int y = ky + h < n ? ky + h : ky - h;
   const int x = kx + h < n ? kx + h : kx - h;
-  const double v = (double)img[cells * i + (int64_t)y * n + x] * (kappa[x] * kappa[y]);
-  G[2 * t] = (Real)(((kx + ky) & 1) ? -v : v);
-  G[2 * t + 1] = (Real)0;
+  const double kk = kappa[x] * kappa[y];
+  const bool odd = (kx + ky) & 1;
+  for (int i = (int)blockIdx.z; i < n_images; i += (int)gridDim.z) {
+    const double v = (double)img[cells * i + (int64_t)y * n + x] * kk;
+    const int64_t t = cells * i + (int64_t)ky * n + kx;
+    G[2 * t] = (Real)(odd ? -v : v);
+    G[2 * t + 1] = (Real)0;
+  }
 }
 
 // w-stacking: n - 1 at pixel (x, y), n = sqrt(1 - l^2 - m^2), l = (x - n/2) cell,
@@ -77,66 +88,76 @@ __device__ inline double layer_centre(const Geometry &G, int layer) {
 // IDFT(G_{i,l})[y][x] exp(+2 pi i w_l (n - 1))) kappa(x) kappa(y) / sumW_i.  F holds the
 // unshifted inverse FFTs of the n_images L grids (layer fastest).
 template <typename Real>
-__global__ void g2i_stack_kernel(Geometry G, const Real *__restrict__ F,
-                                 const double *__restrict__ kappa, const double *__restrict__ wsum,
-                                 Real *__restrict__ img) {
+__global__ void __launch_bounds__(kPixThreads)
+    g2i_stack_kernel(Geometry G, const Real *__restrict__ F, const double *__restrict__ kappa,
+                     const double *__restrict__ wsum, Real *__restrict__ img) {
   const int n = G.n, L = G.n_layers;
+  const int x = (int)(blockIdx.x * kPixThreads + threadIdx.x), y = (int)blockIdx.y;
+  if (x >= n) return;
   const int64_t cells = (int64_t)n * n;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cells * G.n_images) return;
-  const int i = (int)(t / cells);
-  const int64_t r = t - (int64_t)i * cells;
-  const int y = (int)(r / n), x = (int)(r - (int64_t)y * n);
   const int h = n / 2;
   const int ys = y + h < n ? y + h : y - h;
   const int xs = x + h < n ? x + h : x - h;
   double nm1 = 0.0;
-  double acc = 0.0;
-  if (n_minus_1(G, x, y, nm1)) {
-    for (int l = 0; l < L; ++l) {
-      const int64_t e = 2 * (cells * ((int64_t)i * L + l) + (int64_t)ys * n + xs);
-      const double re = (double)F[e], im = (double)F[e + 1];
-      double sn, cs;
-      sincospi(2.0 * layer_centre(G, l) * nm1, &sn, &cs);
-      acc += re * cs - im * sn;  // Re((re + i im)(cs + i sn))
+  const bool sky = n_minus_1(G, x, y, nm1);
+  const double kk = kappa[x] * kappa[y];
+  for (int i = (int)blockIdx.z; i < G.n_images; i += (int)gridDim.z) {
+    double acc = 0.0;
+    if (sky) {
+      for (int l = 0; l < L; ++l) {
+        const int64_t e = 2 * (cells * ((int64_t)i * L + l) + (int64_t)ys * n + xs);
+        const double re = (double)F[e], im = (double)F[e + 1];
+        double sn, cs;
+        sincospi(2.0 * layer_centre(G, l) * nm1, &sn, &cs);
+        acc += re * cs - im * sn;  // Re((re + i im)(cs + i sn))
+      }
     }
+    double scale = kk;
+    if (wsum != nullptr) {
+      const double s = wsum[i];
+      scale = s != 0.0 ? scale / s : 0.0;
+    }
+    const double v = ((x + y) & 1) ? -acc : acc;
+    img[cells * i + (int64_t)y * n + x] = (Real)(v * scale);
   }
-  double scale = kappa[x] * kappa[y];
-  if (wsum != nullptr) {
-    const double s = wsum[i];
-    scale = s != 0.0 ? scale / s : 0.0;
-  }
-  const double v = ((x + y) & 1) ? -acc : acc;
-  img[t] = (Real)(v * scale);
 }
 
 // Image -> grids with w-stacking: layer l of image i gets the shifted, sign-flipped
 // kappa kappa I exp(-2 pi i w_l (n - 1)) (then forward FFTs, as for one grid).
 template <typename Real>
-__global__ void i2g_stack_kernel(Geometry G, const Real *__restrict__ img,
-                                 const double *__restrict__ kappa, Real *__restrict__ Gr) {
+__global__ void __launch_bounds__(kPixThreads)
+    i2g_stack_kernel(Geometry G, const Real *__restrict__ img, const double *__restrict__ kappa,
+                     Real *__restrict__ Gr) {
   const int n = G.n, L = G.n_layers;
+  const int kx = (int)(blockIdx.x * kPixThreads + threadIdx.x), ky = (int)blockIdx.y;
+  if (kx >= n) return;
   const int64_t cells = (int64_t)n * n;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cells * G.n_grids) return;
-  const int g = (int)(t / cells);
-  const int i = g / L, l = g - i * L;
-  const int64_t r = t - (int64_t)g * cells;
-  const int ky = (int)(r / n), kx = (int)(r - (int64_t)ky * n);
   const int h = n / 2;
   const int y = ky + h < n ? ky + h : ky - h;
   const int x = kx + h < n ? kx + h : kx - h;
-  const double v = (double)img[cells * i + (int64_t)y * n + x] * (kappa[x] * kappa[y]);
-  double nm1 = 0.0, re = 0.0, im = 0.0;
-  if (n_minus_1(G, x, y, nm1)) {
-    double sn, cs;
-    sincospi(2.0 * layer_centre(G, l) * nm1, &sn, &cs);
-    re = v * cs;
-    im = -v * sn;
-  }
+  const double kk = kappa[x] * kappa[y];
+  double nm1 = 0.0;
+  const bool sky = n_minus_1(G, x, y, nm1);
   const bool odd = (kx + ky) & 1;
-  Gr[2 * t] = (Real)(odd ? -re : re);
-  Gr[2 * t + 1] = (Real)(odd ? -im : im);
+  for (int g = (int)blockIdx.z; g < G.n_grids; g += (int)gridDim.z) {
+    const int i = g / L, l = g - i * L;
+    const double v = (double)img[cells * i + (int64_t)y * n + x] * kk;
+    double re = 0.0, im = 0.0;
+    if (sky) {
+      double sn, cs;
+      sincospi(2.0 * layer_centre(G, l) * nm1, &sn, &cs);
+      re = v * cs;
+      im = -v * sn;
+    }
+    const int64_t t = cells * g + (int64_t)ky * n + kx;
+    Gr[2 * t] = (Real)(odd ? -re : re);
+    Gr[2 * t + 1] = (Real)(odd ? -im : im);
+  }
+}
+
+inline dim3 pixel_grid(int n, int planes) {
+  return dim3((unsigned)((n + kPixThreads - 1) / kPixThreads), (unsigned)n,
+              std::min((unsigned)planes, kMaxGridZ));
 }
 
 }  // namespace
@@ -144,48 +165,46 @@ __global__ void i2g_stack_kernel(Geometry G, const Real *__restrict__ img,
 hipError_t launch_g2i_correct(const wproj_kernels *k, const void *fgrid, void *image,
                               const double *wsum, hipStream_t s) {
   const int n = k->params.n, ni = k->params.n_images;
-  const int64_t total = (int64_t)n * n * ni;
-  const unsigned blocks = (unsigned)((total + 255) / 256);
+  const dim3 grid = pixel_grid(n, ni), block(kPixThreads);
   if (k->params.w_mode == WPROJ_W_STACK) {
     if (k->params.precision == WPROJ_F64)
-      hipLaunchKernelGGL(g2i_stack_kernel<double>, dim3(blocks), dim3(256), 0, s, k->geo,
-                         (const double *)fgrid, k->d_kappa, wsum, (double *)image);
+      hipLaunchKernelGGL(g2i_stack_kernel<double>, grid, block, 0, s, k->geo, (const double *)fgrid,
+                         k->d_kappa, wsum, (double *)image);
     else
-      hipLaunchKernelGGL(g2i_stack_kernel<float>, dim3(blocks), dim3(256), 0, s, k->geo,
-                         (const float *)fgrid, k->d_kappa, wsum, (float *)image);
+      hipLaunchKernelGGL(g2i_stack_kernel<float>, grid, block, 0, s, k->geo, (const float *)fgrid,
+                         k->d_kappa, wsum, (float *)image);
     return hipGetLastError();
   }
   if (k->params.precision == WPROJ_F64)
-    hipLaunchKernelGGL(g2i_kernel<double>, dim3(blocks), dim3(256), 0, s, n, ni,
-                       (const double *)fgrid, k->d_kappa, wsum, (double *)image);
+    hipLaunchKernelGGL(g2i_kernel<double>, grid, block, 0, s, n, ni, (const double *)fgrid, k->d_kappa,
+                       wsum, (double *)image);
   else
-    hipLaunchKernelGGL(g2i_kernel<float>, dim3(blocks), dim3(256), 0, s, n, ni,
-                       (const float *)fgrid, k->d_kappa, wsum, (float *)image);
+    hipLaunchKernelGGL(g2i_kernel<float>, grid, block, 0, s, n, ni, (const float *)fgrid, k->d_kappa,
+                       wsum, (float *)image);
   return hipGetLastError();
 }
 
 hipError_t launch_i2g_precorrect(const wproj_kernels *k, const void *image, void *grid,
                                  hipStream_t s) {
   const int n = k->params.n, ni = k->params.n_images;
+  const dim3 block(kPixThreads);
   if (k->params.w_mode == WPROJ_W_STACK) {
-    const int64_t total = (int64_t)n * n * k->geo.n_grids;
-    const unsigned blocks = (unsigned)((total + 255) / 256);
+    const dim3 g3 = pixel_grid(n, k->geo.n_grids);
     if (k->params.precision == WPROJ_F64)
-      hipLaunchKernelGGL(i2g_stack_kernel<double>, dim3(blocks), dim3(256), 0, s, k->geo,
-                         (const double *)image, k->d_kappa, (double *)grid);
+      hipLaunchKernelGGL(i2g_stack_kernel<double>, g3, block, 0, s, k->geo, (const double *)image,
+                         k->d_kappa, (double *)grid);
     else
-      hipLaunchKernelGGL(i2g_stack_kernel<float>, dim3(blocks), dim3(256), 0, s, k->geo,
-                         (const float *)image, k->d_kappa, (float *)grid);
+      hipLaunchKernelGGL(i2g_stack_kernel<float>, g3, block, 0, s, k->geo, (const float *)image,
+                         k->d_kappa, (float *)grid);
     return hipGetLastError();
   }
-  const int64_t total = (int64_t)n * n * ni;
-  const unsigned blocks = (unsigned)((total + 255) / 256);
+  const dim3 g3 = pixel_grid(n, ni);
   if (k->params.precision == WPROJ_F64)
-    hipLaunchKernelGGL(i2g_kernel<double>, dim3(blocks), dim3(256), 0, s, n, ni,
-                       (const double *)image, k->d_kappa, (double *)grid);
+    hipLaunchKernelGGL(i2g_kernel<double>, g3, block, 0, s, n, ni, (const double *)image, k->d_kappa,
+                       (double *)grid);
   else
-    hipLaunchKernelGGL(i2g_kernel<float>, dim3(blocks), dim3(256), 0, s, n, ni,
-                       (const float *)image, k->d_kappa, (float *)grid);
+    hipLaunchKernelGGL(i2g_kernel<float>, g3, block, 0, s, n, ni, (const float *)image, k->d_kappa,
+                       (float *)grid);
   return hipGetLastError();
 }
 

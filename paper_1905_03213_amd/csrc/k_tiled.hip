@@ -454,31 +454,32 @@ template <typename Real>
 __global__ void __launch_bounds__(256)
     tile_reduce_kernel(Geometry G, BinShape B, int rows, const typename Cx<Real>::T *__restrict__ partial,
                        const uint32_t *__restrict__ choff, Real *grid) {
+  // blockIdx.x * 256 + threadIdx.x is the column, blockIdx.y the row, blockIdx.z steps
+  // through the grids
+  const int X = (int)(blockIdx.x * 256 + threadIdx.x), Y = (int)blockIdx.y;
+  if (X >= G.n) return;
   const int64_t cells = (int64_t)G.n * G.n;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cells * G.n_grids) return;
-  const int img = (int)(t / cells);
-  const int64_t c = t - (int64_t)img * cells;
-  const int Y = (int)(c / G.n), X = (int)(c - (int64_t)Y * G.n);
   const int T = B.tile;
-  const int tx = X / T, ty = Y / T, lx = X - tx * T, ly = Y - ty * T;
-  double sr = 0.0, si = 0.0;
-  for (int dy = 0; dy <= ty && ly + dy * T < rows; ++dy) {
-    for (int dx = 0; dx <= tx && lx + dx * T < rows; ++dx) {
-      const int64_t tile = ((int64_t)img * B.nty + (ty - dy)) * B.ntx + (tx - dx);
-      const int off = (ly + dy * T) * rows + (lx + dx * T);
-      const uint32_t i1 = choff[tile + 1];
-      for (uint32_t i = choff[tile]; i < i1; ++i) {
-        const auto v = partial[(size_t)i * rows * rows + off];
-        sr += (double)v.x;
-        si += (double)v.y;
+  const int tx = X >> B.log2_tile, ty = Y >> B.log2_tile, lx = X & (T - 1), ly = Y & (T - 1);
+  for (int img = (int)blockIdx.z; img < G.n_grids; img += (int)gridDim.z) {
+    double sr = 0.0, si = 0.0;
+    for (int dy = 0; dy <= ty && ly + dy * T < rows; ++dy) {
+      for (int dx = 0; dx <= tx && lx + dx * T < rows; ++dx) {
+        const int64_t tile = ((int64_t)img * B.nty + (ty - dy)) * B.ntx + (tx - dx);
+        const int off = (ly + dy * T) * rows + (lx + dx * T);
+        const uint32_t i1 = choff[tile + 1];
+        for (uint32_t i = choff[tile]; i < i1; ++i) {
+          const auto v = partial[(size_t)i * rows * rows + off];
+          sr += (double)v.x;
+          si += (double)v.y;
+        }
       }
     }
-  }
-  if (sr != 0.0 || si != 0.0) {
-    Real *g = grid + 2 * t;
-    g[0] = (Real)((double)g[0] + sr);
-    g[1] = (Real)((double)g[1] + si);
+    if (sr != 0.0 || si != 0.0) {
+      Real *g = grid + 2 * (cells * img + (int64_t)Y * G.n + X);
+      g[0] = (Real)((double)g[0] + sr);
+      g[1] = (Real)((double)g[1] + si);
+    }
   }
 }
 
@@ -514,8 +515,9 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
 template <typename Real>
 hipError_t launch_reduce(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
                          const BinWorkspace &W, void *grid, hipStream_t s) {
-  const int64_t total = (int64_t)k->params.n * k->params.n * k->geo.n_grids;
-  hipLaunchKernelGGL(tile_reduce_kernel<Real>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+  const dim3 grid3((unsigned)((k->params.n + 255) / 256), (unsigned)k->params.n,
+                   (unsigned)std::min<int64_t>(k->geo.n_grids, 65535));
+  hipLaunchKernelGGL(tile_reduce_kernel<Real>, grid3, dim3(256), 0,
                      s, k->geo, B, ts.rows, (const typename Cx<Real>::T *)W.partial, W.choff,
                      (Real *)grid);
   return hipGetLastError();
