@@ -292,6 +292,31 @@ def main():
         planned_grid_ms = sum(pph[ph][0] / max(pph[ph][1], 1) for ph in ("grid", "reduce"))
         planned_degrid_ms = pph["degrid"][0] / max(pph["degrid"][1], 1)
 
+        # the same step with stable bins (records in input order inside each bin: a radix
+        # sort of the bin keys and a gather instead of the atomic-slot scatter)
+        ks = W.make_kernels({**params, "tile": tile, "chunk": chunk, "stable_bins": True})
+        ws_s = ks.workspace(nvis)
+        W.grid(ks, uvw, vis32, wt32, g, workspace=ws_s)
+        torch.cuda.synchronize()
+        ks.profile(True)
+        ks.profile_read()
+        ev0.record(stream)
+        for _ in range(reps):
+            g.zero_()
+            sw.zero_()
+            W.grid(ks, uvw, vis32, wt32, g, weight_sum=sw, workspace=ws_s)
+            W.image(ks, W.GRID_TO_IMAGE, g, img, sw, workspace=ws_s)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        sph = ks.profile_read()
+        ks.profile(False)
+        stable = {"ms_per_step": ev0.elapsed_time(ev1) / reps,
+                  "bin_ms": sph["bin"][0] / max(sph["bin"][1], 1)}
+        stable["mvis_per_s"] = n_valid / stable["ms_per_step"] / 1e3
+        log(f"stable bins: {stable['ms_per_step']:.3f} ms/step (bin {stable['bin_ms']:.3f} ms)")
+        del ws_s
+        ks.free()
+
         # rows regrouped by baseline (Eqs. 5 and 6) and the rows of uvw and visibilities
         # gathered into that order: the paper's GPU-side data preparation, on the same rows
         src = wl.sources
@@ -343,6 +368,7 @@ def main():
                        "vmem_frac": TAP_BYTES_PER_VIS * n_valid / (degrid_ms * 1e-3) / peak_vmem},
             "planned": {"grid_ms": planned_grid_ms, "grid_mvis_per_s": n_valid / planned_grid_ms / 1e3,
                         "degrid_ms": planned_degrid_ms},
+            "stable_bins": stable,
             "run_accumulation": runs,
             "regroup_by_baseline": {"rows": n_t * n_bl, "ms": regroup_ms, "gather_uvw_vis_ms": gather_ms,
                                     "gather_gb_per_s": gather_bytes / gather_ms / 1e6}})

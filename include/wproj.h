@@ -130,6 +130,18 @@ typedef struct {
                                rows apart (one channel per row in time order: the same
                                baseline recurs every few hundred rows, in the same bin for
                                minutes).  wproj_autotune times both. */
+  int32_t stable_bins;      /* 0 or 1: the order of records inside a bin (the same bins either
+                               way).  0: each visibility's place comes from the count atomics,
+                               so it follows their timing and FP32 grids of two runs agree to
+                               rounding.  1: a stable counting sort, as the paper's regroup
+                               keeps a baseline's rows in time order (Eq. 5 and 6): the bin
+                               keys are sorted by a least-significant-digit radix sort (8 bits
+                               a pass) and the records gathered in sorted order, so a bin keeps
+                               its visibilities in input order and every grid is reproducible
+                               bit for bit.  Slower (the sort reads and writes 8 bytes per
+                               visibility and pass) and 16 more workspace bytes per
+                               visibility.  Tiled algorithm only (ignored by the plain
+                               one). */
   int32_t reserved[1];      /* must be zero */
 } wproj_params;
 
@@ -350,6 +362,17 @@ int wproj_plan_create(const wproj_kernels *k, int64_t nvis, const double *uvw, c
 int wproj_plan_free(wproj_plan *plan);
 int wproj_grid_planned(const wproj_plan *plan, const void *vis, void *grid, void *stream);
 int wproj_degrid_planned(const wproj_plan *plan, const void *model_grid, void *vis_out, void *stream);
+
+/*
+ * The binned order a plan keeps (the counting sort that Eq. 5 and 6 describe for the
+ * paper's baseline regroup, keyed here by bin): rows[i] (uint32, device, nvis entries) =
+ * the row whose record is i-th in bin order, for i below the number of rows the plan
+ * grids; the remaining entries are set to 0xffffffff.  Bins run in key order (image,
+ * tile row, tile column, then w-plane when planes are binned apart), each bin's rows
+ * contiguous; with stable_bins a bin's rows are in increasing order, otherwise in the
+ * order the count atomics handed out.  Errors: WPROJ_EINVAL, WPROJ_EHIP.
+ */
+int wproj_plan_rows(const wproj_plan *plan, uint32_t *rows, void *stream);
 
 /*
  * Per-visibility footprint: the uvw -> grid step every gridding and degridding call

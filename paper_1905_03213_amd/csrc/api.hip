@@ -151,6 +151,8 @@ int validate(const wproj_params *p, std::vector<int32_t> &supp) {
     return fail(WPROJ_EINVAL, "accumulate_runs must be 0 or 1");
   if (p->bin_aggregate != 0 && p->bin_aggregate != 1)
     return fail(WPROJ_EINVAL, "bin_aggregate must be 0 or 1");
+  if (p->stable_bins != 0 && p->stable_bins != 1)
+    return fail(WPROJ_EINVAL, "stable_bins must be 0 or 1");
   for (int r : p->reserved)
     if (r != 0) return fail(WPROJ_EINVAL, "reserved fields must be zero");
   supp.assign(p->n_wplanes, p->support);
@@ -225,6 +227,7 @@ BinShape bin_shape(const wproj_kernels *k) {
   B.kw = k->plane_in_key ? k->params.n_wplanes : 1;
   B.chunk = k->chunk;
   B.aggregate = k->bin_aggregate;
+  B.stable = k->stable_bins;
   // a fixed support with a kernel of its own, and sub-kernel numbers that fit above the
   // LDS offset
   const int64_t n_sub = (int64_t)k->params.n_wplanes * k->params.oversample * k->params.oversample;
@@ -235,11 +238,9 @@ BinShape bin_shape(const wproj_kernels *k) {
   return B;
 }
 
-// Bins the 32-bit keys can number: with a Hermitian fold the key pass keeps the fold
-// flag of fixed-support records in the key's top bit.
-int64_t max_keys(const wproj_kernels *k) {
-  return k->params.w_mode != WPROJ_W_LINEAR ? (int64_t)0x7fffffffll : (int64_t)0xffffffffll;
-}
+// Bins the keys can number: the key pass stores the fold flag of fixed-support records in
+// the top bit of their 32-bit key word, and the scatter reads it there in every w mode.
+int64_t max_keys(const wproj_kernels *) { return (int64_t)0x7fffffffll; }
 
 // Lays the binning buffers out from `base` (nullptr: sizes only); returns total bytes.
 int64_t carve(const wproj_kernels *k, int64_t nvis, char *base, BinWorkspace &W) {
@@ -262,7 +263,8 @@ int64_t carve(const wproj_kernels *k, int64_t nvis, char *base, BinWorkspace &W)
   W.nch = (uint32_t *)take(4 * B.n_tiles);
   W.choff = (uint32_t *)take(4 * (B.n_tiles + 1));
   W.items = (WorkItem *)take((int64_t)sizeof(WorkItem) * max_items);
-  W.scan_tmp = (uint32_t *)take(4 * scan_temp_words(std::max(B.n_keys, B.n_tiles)));
+  const int64_t digit_slots = B.stable ? radix_digit_slots(nvis) : 0;
+  W.scan_tmp = (uint32_t *)take(4 * scan_temp_words(std::max({B.n_keys, B.n_tiles, digit_slots})));
   W.counter = (uint32_t *)take(4);
   W.order = (uint32_t *)take(4 * max_items);
   W.order_cnt = (uint32_t *)take(4 * 2 * kOrderBuckets);
@@ -272,6 +274,12 @@ int64_t carve(const wproj_kernels *k, int64_t nvis, char *base, BinWorkspace &W)
   W.partial = take(max_items * (int64_t)ts.rows * ts.rows * cplx);
   W.wslots = (double *)take(8 * kSlots * (int64_t)k->params.n_images);
   W.cslots = (unsigned long long *)take(8 * 3 * kSlots);
+  for (int i = 0; i < 2; ++i) {
+    W.sort_keys[i] = B.stable ? (uint32_t *)take(4 * nvis) : nullptr;
+    W.sort_vals[i] = B.stable ? (uint32_t *)take(4 * nvis) : nullptr;
+  }
+  W.digit_count = B.stable ? (uint32_t *)take(4 * digit_slots) : nullptr;
+  W.digit_off = B.stable ? (uint32_t *)take(4 * (digit_slots + 1)) : nullptr;
   return off;
 }
 
@@ -296,6 +304,7 @@ int64_t workspace_bytes_for(const wproj_kernels *k, int64_t nvis) {
     tmp.geo = k->geo;
     tmp.s_max = k->s_max;
     tmp.uniform_support = k->uniform_support;
+    tmp.stable_bins = k->stable_bins;
     for (int tile : kTuneTiles) {
       if (tile_shape(k, tile).lds_bytes + 256 > k->max_lds) continue;  // never tuned to
       tmp.tile = tile;
@@ -428,6 +437,7 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
   }
   if (params->chunk) k->chunk = params->chunk;
   k->bin_aggregate = params->bin_aggregate;
+  k->stable_bins = params->stable_bins;
 
   Geometry &G = k->geo;
   G.n = n;
@@ -612,7 +622,7 @@ int wproj_grid(const wproj_kernels *k, int64_t nvis, const double *uvw, const vo
                 (long long)k->n_taps);
   const BinShape B = bin_shape(k);
   if (B.n_keys >= max_keys(k))
-    return fail(WPROJ_EUNSUPPORTED, "%lld bins (images x tiles) exceed the tiled gridder's 32-bit keys",
+    return fail(WPROJ_EUNSUPPORTED, "%lld bins (images x tiles) exceed the tiled gridder's 31-bit keys",
                 (long long)B.n_keys);
   BinWorkspace W;
   carve(k, nvis, (char *)workspace, W);
@@ -762,7 +772,7 @@ int wproj_degrid(const wproj_kernels *k, int64_t nvis, const double *uvw, const 
                 (long long)k->n_taps);
   BinShape B = bin_shape(k);
   if (B.n_keys >= max_keys(k))
-    return fail(WPROJ_EUNSUPPORTED, "%lld bins (images x tiles) exceed the tiled degridder's 32-bit keys",
+    return fail(WPROJ_EUNSUPPORTED, "%lld bins (images x tiles) exceed the tiled degridder's 31-bit keys",
                 (long long)B.n_keys);
   BinWorkspace W;
   carve(k, nvis, (char *)workspace, W);
@@ -883,7 +893,7 @@ int wproj_plan_create(const wproj_kernels *k, int64_t nvis, const double *uvw, c
   if (p->B.n_keys >= max_keys(k)) {
     const long long n_keys = (long long)p->B.n_keys;
     delete p;
-    return fail(WPROJ_EUNSUPPORTED, "%lld bins exceed the tiled path's 32-bit keys", n_keys);
+    return fail(WPROJ_EUNSUPPORTED, "%lld bins exceed the tiled path's 31-bit keys", n_keys);
   }
   carve(k, nvis, (char *)workspace, p->W);
   if (nvis > 0) {
@@ -920,6 +930,17 @@ int wproj_grid_planned(const wproj_plan *p, const void *vis, void *grid, void *s
   }
   PhaseTimer pt(p->k, WPROJ_PHASE_REDUCE, s);
   HIP_TRY(launch_tile_reduce(p->k, p->B, p->W, grid, s));
+  return WPROJ_OK;
+}
+
+int wproj_plan_rows(const wproj_plan *p, uint32_t *rows, void *stream) {
+  g_err.clear();
+  if (!p) return fail(WPROJ_EINVAL, "plan is NULL");
+  if (p->nvis > 0 && !rows) return fail(WPROJ_EINVAL, "rows is NULL");
+  int rc = check_device(p->k);
+  if (rc != WPROJ_OK) return rc;
+  if (p->nvis == 0) return WPROJ_OK;
+  HIP_TRY(launch_plan_rows(p->k, p->B, p->W, p->nvis, rows, (hipStream_t)stream));
   return WPROJ_OK;
 }
 

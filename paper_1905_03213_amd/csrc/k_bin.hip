@@ -13,7 +13,9 @@
 //   work list    each tile's record range split into chunks of at most `chunk` records.
 // Count atomics are aggregated over runs of a wavefront's lanes that share a key, so a
 // record's place inside its bin follows the order in which the runs' atomics land (the
-// bin's contents are fixed, their order is not).  With a fixed support (records carry
+// bin's contents are fixed, their order is not).  Stable bins (BinShape::stable) replace
+// the scatter by a stable radix sort of the keys and a gather in sorted order, so that a
+// bin keeps its visibilities in input order.  With a fixed support (records carry
 // the packed LDS offset and sub-kernel number) the key pass also stores each
 // visibility's key and packed word next to its slot, so the scatter reads 12 bytes
 // instead of the 24-byte uvw and skips the FP64 footprint; otherwise the scatter
@@ -401,25 +403,22 @@ __global__ void __launch_bounds__(kAggThreads)
   }
 }
 
-// COMPACT: the key pass stored each visibility's key and packed first word (fixed
-// support S_fix, whose sub-kernel number n starts at tap n S_fix^2); otherwise the
-// footprint is computed again from the same inputs, with the same outcome.  A
-// visibility's key is loaded first, so that the bin offset it indexes is fetched while
-// the rest of the record's inputs arrive; rows that are not gridded load nothing more.
+// The record of visibility j and its bin key; false when j is not gridded.  COMPACT: the
+// key pass stored each visibility's key and packed first word (fixed support S_fix, whose
+// sub-kernel number n starts at tap n S_fix^2); otherwise the footprint is computed again
+// from the same inputs, with the same outcome.  The key is loaded first, so that the bin
+// offset it indexes is fetched while the rest of the record's inputs arrive; rows that
+// are not gridded load nothing more.
 template <typename Real, typename Cplx, typename Rec, bool COMPACT>
-__global__ void __launch_bounds__(kBinBlock)
-    scatter_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
-                   const Cplx *__restrict__ vis, const Real *__restrict__ wt,
-                   const int64_t *__restrict__ img_off, const uint32_t *__restrict__ slots,
-                   const uint32_t *__restrict__ offset, int S_fix, Rec *__restrict__ rec) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nvis) return;
-  Rec r;
-  uint32_t key;
+__device__ inline bool make_record(const Geometry &G, const BinShape &B, int64_t nvis,
+                                   const double *__restrict__ uvw, const Cplx *__restrict__ vis,
+                                   const Real *__restrict__ wt, const int64_t *__restrict__ img_off,
+                                   const uint32_t *__restrict__ slots, int S_fix, int64_t j, Rec &r,
+                                   uint32_t &key) {
   bool fold;
   if constexpr (COMPACT) {
     key = slots[nvis + j];
-    if (key == kInvalid) return;
+    if (key == kInvalid) return false;
     fold = (key & kFoldBit) != 0;
     key &= ~kFoldBit;
     r.lds = slots[2 * nvis + j];
@@ -427,10 +426,10 @@ __global__ void __launch_bounds__(kBinBlock)
       r.tap = (r.lds >> kLdsBits) * (uint32_t)(S_fix * S_fix) | ((uint32_t)(S_fix - 1) << kTapBits);
   } else {
     const int img = image_of(img_off, G.n_images, j);
-    if (img < 0) return;
+    if (img < 0) return false;
     Footprint f;
     const Real w = wt ? wt[j] : Real(1);
-    if (classify(G, uvw + 3 * j, w, f) != kGridded) return;
+    if (classify(G, uvw + 3 * j, w, f) != kGridded) return false;
     fold = f.fold;
     key = bin_key(G, B, img, f);
     const int S = G.supp[f.p];
@@ -449,7 +448,182 @@ __global__ void __launch_bounds__(kBinBlock)
     // row-carrying records mark a folded row by a negative weight
     set_plan(r, fold ? -w : w, (uint32_t)j);
   }
-  rec[offset[key] + slots[j]] = r;
+  return true;
+}
+
+// Record of visibility j to offset[key] + its slot.
+template <typename Real, typename Cplx, typename Rec, bool COMPACT>
+__global__ void __launch_bounds__(kBinBlock)
+    scatter_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
+                   const Cplx *__restrict__ vis, const Real *__restrict__ wt,
+                   const int64_t *__restrict__ img_off, const uint32_t *__restrict__ slots,
+                   const uint32_t *__restrict__ offset, int S_fix, Rec *__restrict__ rec) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nvis) return;
+  Rec r;
+  uint32_t key;
+  if (make_record<Real, Cplx, Rec, COMPACT>(G, B, nvis, uvw, vis, wt, img_off, slots, S_fix, j, r, key))
+    rec[offset[key] + slots[j]] = r;
+}
+
+// ---- stable binning: least-significant-digit radix sort of the bin keys ----
+//
+// Each visibility's sort key is its bin key, or n_keys when it is not gridded (so those
+// sort last); its value is its index.  A pass sorts by one 8-bit digit and is stable:
+// every block counts the digits of its kRadixTile consecutive elements, an exclusive scan
+// of the counts laid out digit-major gives each (digit, block) its first output place,
+// and within a block the elements keep their order (wavefront w takes the w-th quarter of
+// the block's range, 64 elements a step; an element's rank among the equal digits before
+// it is the count over earlier steps, kept in LDS per wavefront, plus the equal lanes
+// below it in its step, found with one ballot per digit bit).  After the last pass the
+// values list the gridded visibilities bin by bin, each bin in input order, and
+// gather_kernel writes record p from visibility values[p].
+constexpr int kRadixBits = 8;
+constexpr int kRadixDigits = 1 << kRadixBits;
+constexpr int kRadixThreads = 256;
+constexpr int kRadixWaves = kRadixThreads / 64;
+constexpr int kRadixSteps = 16;                          // 64-element steps per wavefront
+constexpr int kRadixTile = kRadixThreads * kRadixSteps;  // elements per block
+static_assert(kRadixThreads == kRadixDigits, "one thread per digit in the block-level steps");
+
+// Lanes of the wavefront whose (valid) digit equals this lane's.
+__device__ inline uint64_t same_digit_lanes(uint32_t d, bool valid) {
+  uint64_t m = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < kRadixBits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t on = __ballot(bit);
+    m &= bit ? on : ~on;
+  }
+  return m;
+}
+
+// Set lanes of m below this lane.
+__device__ inline uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Element e of the block's range: wavefront w's quarter, step i, lane.
+__device__ inline int64_t radix_elem(int w, int i, int lane) {
+  return (int64_t)blockIdx.x * kRadixTile + (int64_t)w * (64 * kRadixSteps) + i * 64 + lane;
+}
+
+template <typename Real, bool COMPACT>
+__global__ void __launch_bounds__(kBinBlock)
+    sort_key_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
+                    const Real *__restrict__ wt, const int64_t *__restrict__ img_off,
+                    const uint32_t *__restrict__ slots, uint32_t *__restrict__ keys) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nvis) return;
+  uint32_t key = (uint32_t)B.n_keys;
+  if constexpr (COMPACT) {
+    const uint32_t kw = slots[nvis + j];
+    if (kw != kInvalid) key = kw & ~kFoldBit;
+  } else {
+    const int img = image_of(img_off, G.n_images, j);
+    if (img >= 0) {
+      Footprint f;
+      const Real w = wt ? wt[j] : Real(1);
+      if (classify(G, uvw + 3 * j, w, f) == kGridded) key = bin_key(G, B, img, f);
+    }
+  }
+  keys[j] = key;
+}
+
+// count[d * n_blocks + block] = elements of the block whose digit is d.
+__global__ void __launch_bounds__(kRadixThreads)
+    radix_count_kernel(const uint32_t *__restrict__ keys, int64_t n, int shift, int64_t n_blocks,
+                       uint32_t *__restrict__ count) {
+  __shared__ uint32_t h[kRadixDigits];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t key[kRadixSteps];
+#pragma unroll
+  for (int i = 0; i < kRadixSteps; ++i) {
+    const int64_t e = radix_elem(w, i, lane);
+    key[i] = e < n ? keys[e] : 0u;
+  }
+#pragma unroll
+  for (int i = 0; i < kRadixSteps; ++i) {
+    const bool valid = radix_elem(w, i, lane) < n;
+    const uint32_t d = (key[i] >> shift) & (uint32_t)(kRadixDigits - 1);
+    const uint64_t m = same_digit_lanes(d, valid);
+    if (valid && lanes_below(m) == 0u) atomicAdd(&h[d], (uint32_t)__popcll(m));
+  }
+  __syncthreads();
+  count[(int64_t)threadIdx.x * n_blocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// One stable pass: element e goes to digit_off[d * n_blocks + block] + (elements of digit
+// d before it in the block).  vin == nullptr: the values are the element indices;
+// kout == nullptr: the keys are not needed after this pass.
+__global__ void __launch_bounds__(kRadixThreads)
+    radix_place_kernel(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
+                       int shift, int64_t n_blocks, const uint32_t *__restrict__ digit_off,
+                       uint32_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+  __shared__ uint32_t cnt[kRadixWaves][kRadixDigits];
+  for (int i = threadIdx.x; i < kRadixWaves * kRadixDigits; i += kRadixThreads) cnt[i / kRadixDigits][i % kRadixDigits] = 0u;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t key[kRadixSteps], val[kRadixSteps], rank[kRadixSteps];
+#pragma unroll
+  for (int i = 0; i < kRadixSteps; ++i) {
+    const int64_t e = radix_elem(w, i, lane);
+    key[i] = e < n ? kin[e] : 0u;
+    val[i] = e < n ? (vin ? vin[e] : (uint32_t)e) : 0u;
+  }
+  // rank of each element among the wavefront's earlier elements of its digit; the lanes
+  // of a step read the running count before its first lane of each digit adds the step's
+  // share (one wavefront's LDS accesses take effect in program order)
+#pragma unroll
+  for (int i = 0; i < kRadixSteps; ++i) {
+    const bool valid = radix_elem(w, i, lane) < n;
+    const uint32_t d = (key[i] >> shift) & (uint32_t)(kRadixDigits - 1);
+    const uint64_t m = same_digit_lanes(d, valid);
+    const uint32_t below = lanes_below(m);
+    const uint32_t before = cnt[w][d];
+    rank[i] = before + below;
+    if (valid && below == 0u) cnt[w][d] = before + (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  // first output place of wavefront v's elements of digit d (thread d)
+  {
+    const int d = threadIdx.x;
+    uint32_t start = digit_off[(int64_t)d * n_blocks + blockIdx.x];
+    for (int v = 0; v < kRadixWaves; ++v) {
+      const uint32_t c = cnt[v][d];
+      cnt[v][d] = start;
+      start += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kRadixSteps; ++i) {
+    if (radix_elem(w, i, lane) < n) {
+      const uint32_t d = (key[i] >> shift) & (uint32_t)(kRadixDigits - 1);
+      const uint32_t pos = cnt[w][d] + rank[i];
+      if (kout) kout[pos] = key[i];
+      vout[pos] = val[i];
+    }
+  }
+}
+
+// Record p (below the number of gridded visibilities, *total) from visibility order[p].
+template <typename Real, typename Cplx, typename Rec, bool COMPACT>
+__global__ void __launch_bounds__(kBinBlock)
+    gather_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
+                  const Cplx *__restrict__ vis, const Real *__restrict__ wt,
+                  const int64_t *__restrict__ img_off, const uint32_t *__restrict__ slots,
+                  const uint32_t *__restrict__ order, const uint32_t *__restrict__ total, int S_fix,
+                  Rec *__restrict__ rec) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)*total) return;
+  Rec r;
+  uint32_t key;
+  if (make_record<Real, Cplx, Rec, COMPACT>(G, B, nvis, uvw, vis, wt, img_off, slots, S_fix,
+                                            (int64_t)order[p], r, key))
+    rec[p] = r;
 }
 
 // Adds the per-slot partial weight sums and counters into the caller's outputs, in a
@@ -611,12 +785,64 @@ __global__ void __launch_bounds__(256)
   if (i < n) order[base[c] + rank] = (uint32_t)i;
 }
 
+template <typename Rec>
+__global__ void __launch_bounds__(256)
+    plan_rows_kernel(const Rec *__restrict__ rec, const uint32_t *__restrict__ total, int64_t nvis,
+                     uint32_t *__restrict__ rows) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvis) return;
+  rows[i] = i < (int64_t)*total ? get_row(rec[i]) : 0xffffffffu;
+}
+
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
 
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Records in bin order: scattered to offset[key] + slot, or, for stable bins, sorted by
+// key (radix passes over the key's significant bits) and gathered in sorted order.
+template <typename Real, typename Cplx, typename Rec, bool COMPACT>
+hipError_t place_records(const wproj_kernels *k, const BinShape &B, int64_t nvis, const double *uvw,
+                         const void *vis, const void *wt, const int64_t *img_off, const BinWorkspace &W,
+                         int S_fix, hipStream_t s) {
+  const Geometry &G = k->geo;
+  const dim3 grid(nblk(nvis, kBinBlock)), block(kBinBlock);
+  if (!B.stable) {
+    hipLaunchKernelGGL((scatter_kernel<Real, Cplx, Rec, COMPACT>), grid, block, 0, s, G, B, nvis, uvw,
+                       (const Cplx *)vis, (const Real *)wt, img_off, W.slots, W.offset, S_fix, (Rec *)W.rec);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((sort_key_kernel<Real, COMPACT>), grid, block, 0, s, G, B, nvis, uvw, (const Real *)wt,
+                     img_off, W.slots, W.sort_keys[0]);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // keys run from 0 to n_keys (not gridded)
+  int bits = 1;
+  while (bits < 32 && (B.n_keys >> bits) != 0) ++bits;
+  const int64_t n_blocks = (nvis + kRadixTile - 1) / kRadixTile;
+  const int64_t n_counts = n_blocks * kRadixDigits;
+  const uint32_t *vals = nullptr;  // element indices in the first pass
+  int cur = 0;
+  for (int shift = 0; shift < bits; shift += kRadixBits) {
+    const bool last = shift + kRadixBits >= bits;
+    hipLaunchKernelGGL(radix_count_kernel, dim3((unsigned)n_blocks), dim3(kRadixThreads), 0, s,
+                       W.sort_keys[cur], nvis, shift, n_blocks, W.digit_count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_exclusive_scan(W.digit_count, W.digit_off, n_counts, W.scan_tmp, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(radix_place_kernel, dim3((unsigned)n_blocks), dim3(kRadixThreads), 0, s,
+                       W.sort_keys[cur], vals, nvis, shift, n_blocks, W.digit_off,
+                       last ? nullptr : W.sort_keys[cur ^ 1], W.sort_vals[cur ^ 1]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    vals = W.sort_vals[cur ^ 1];
+    cur ^= 1;
+  }
+  hipLaunchKernelGGL((gather_kernel<Real, Cplx, Rec, COMPACT>), grid, block, 0, s, G, B, nvis, uvw,
+                     (const Cplx *)vis, (const Real *)wt, img_off, W.slots, vals, W.offset + B.n_keys, S_fix,
+                     (Rec *)W.rec);
+  return hipGetLastError();
+}
 
 }  // namespace
 
@@ -628,6 +854,10 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
 
 int64_t scan_temp_words(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
+int64_t radix_digit_slots(int64_t nvis) {
+  return std::max<int64_t>(1, (nvis + kRadixTile - 1) / kRadixTile) * kRadixDigits;
+}
+
 // out[i] = sum_{k < i} in[i], out[n] = total (out has n + 1 entries).
 hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
                                  hipStream_t s) {
@@ -636,6 +866,19 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, u
                      tmp);
   hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kScanBlock), 0, s, tmp, tiles, out + n);
   hipLaunchKernelGGL(scan_add_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, out, n, tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_rows(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W, int64_t nvis,
+                            uint32_t *rows, hipStream_t s) {
+  // plans hold row-carrying records: RecordF64 in FP64, RecordF32 otherwise
+  const uint32_t *total = W.offset + B.n_keys;
+  if (k->params.precision == WPROJ_F64)
+    hipLaunchKernelGGL(plan_rows_kernel<RecordF64>, dim3(nblk(nvis, 256)), dim3(256), 0, s,
+                       (const RecordF64 *)W.rec, total, nvis, rows);
+  else
+    hipLaunchKernelGGL(plan_rows_kernel<RecordF32>, dim3(nblk(nvis, 256)), dim3(256), 0, s,
+                       (const RecordF32 *)W.rec, total, nvis, rows);
   return hipGetLastError();
 }
 
@@ -651,7 +894,7 @@ hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, c
   if ((e = launch_fill_u32((uint32_t *)W.cslots, 2 * 3 * kSlots, 0u, s)) != hipSuccess) return e;
   double *wpart = wsum ? W.wslots : nullptr;
   auto *cnt = counters ? W.cslots : nullptr;
-  const dim3 key_grid(nblk(nvis, kBinBlock * kKeyVpt)), grid(nblk(nvis, kBinBlock)), block(kBinBlock);
+  const dim3 key_grid(nblk(nvis, kBinBlock * kKeyVpt)), block(kBinBlock);
   const bool agg = B.aggregate != 0;  // counts aggregated per block in LDS
   const dim3 agg_grid(nblk(nvis, kAggSpan)), agg_block(kAggThreads);
   const bool compact = B.pack_sub != 0;
@@ -695,30 +938,15 @@ hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, c
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = launch_exclusive_scan(W.count, W.offset, B.n_keys, W.scan_tmp, s)) != hipSuccess) return e;
-  if (k->params.precision == WPROJ_F64) {
-    if (compact)
-      hipLaunchKernelGGL((scatter_kernel<double, double2, RecordF64, true>), grid, block, 0, s, G, B, nvis,
-                         uvw, (const double2 *)vis, (const double *)wt, img_off, W.slots, W.offset, S_fix,
-                         (RecordF64 *)W.rec);
-    else
-      hipLaunchKernelGGL((scatter_kernel<double, double2, RecordF64, false>), grid, block, 0, s, G, B, nvis,
-                         uvw, (const double2 *)vis, (const double *)wt, img_off, W.slots, W.offset, S_fix,
-                         (RecordF64 *)W.rec);
-  } else {
-    if (compact && vis)  // W V records of a fixed support: no tap word (12 bytes)
-      hipLaunchKernelGGL((scatter_kernel<float, float2, RecordF32P, true>), grid, block, 0, s, G, B, nvis,
-                         uvw, (const float2 *)vis, (const float *)wt, img_off, W.slots, W.offset, S_fix,
-                         (RecordF32P *)W.rec);
-    else if (compact)
-      hipLaunchKernelGGL((scatter_kernel<float, float2, RecordF32, true>), grid, block, 0, s, G, B, nvis,
-                         uvw, (const float2 *)vis, (const float *)wt, img_off, W.slots, W.offset, S_fix,
-                         (RecordF32 *)W.rec);
-    else
-      hipLaunchKernelGGL((scatter_kernel<float, float2, RecordF32, false>), grid, block, 0, s, G, B, nvis,
-                         uvw, (const float2 *)vis, (const float *)wt, img_off, W.slots, W.offset, S_fix,
-                         (RecordF32 *)W.rec);
-  }
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (k->params.precision == WPROJ_F64)
+    e = compact ? place_records<double, double2, RecordF64, true>(k, B, nvis, uvw, vis, wt, img_off, W, S_fix, s)
+                : place_records<double, double2, RecordF64, false>(k, B, nvis, uvw, vis, wt, img_off, W, S_fix, s);
+  else if (compact && vis)  // W V records of a fixed support: no tap word (12 bytes)
+    e = place_records<float, float2, RecordF32P, true>(k, B, nvis, uvw, vis, wt, img_off, W, S_fix, s);
+  else
+    e = compact ? place_records<float, float2, RecordF32, true>(k, B, nvis, uvw, vis, wt, img_off, W, S_fix, s)
+                : place_records<float, float2, RecordF32, false>(k, B, nvis, uvw, vis, wt, img_off, W, S_fix, s);
+  if (e != hipSuccess) return e;
   // work list: per tile, ceil(records / chunk) items
   hipLaunchKernelGGL(chunk_count_kernel, dim3(nblk(B.n_tiles, 256)), dim3(256), 0, s, W.offset,
                      B.n_tiles, B.kw, B.chunk, W.nch);

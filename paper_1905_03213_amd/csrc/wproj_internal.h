@@ -196,6 +196,7 @@ struct wproj_kernels {
   bool plane_in_key = true; // bin by (tile, plane) rather than tile alone
   int chunk = 2048;         // max records per gridder work item
   int bin_aggregate = 0;    // binning's count aggregation (wproj_params::bin_aggregate)
+  int stable_bins = 0;      // records keep input order inside a bin (wproj_params::stable_bins)
   int n_cu = 256;           // compute units of the device
   size_t max_lds = 65536;   // LDS bytes available to one workgroup
   // phase timing (wproj_profile): recorded (start, stop) event pairs per phase

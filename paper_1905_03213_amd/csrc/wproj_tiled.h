@@ -140,6 +140,7 @@ struct BinShape {
   int chunk;         // max records per work item
   int pack_sub;      // records carry the sub-kernel number in Record::lds (fixed support)
   int aggregate;     // the key pass aggregates counts per block in LDS (wproj_params::bin_aggregate)
+  int stable;        // records keep input order inside a bin (wproj_params::stable_bins)
   int64_t n_tiles;   // n_images * ntx * nty
   int64_t n_keys;    // n_tiles * kw
 };
@@ -167,7 +168,15 @@ struct BinWorkspace {
   void *partial;       // [max_items][rows][rows] complex: each work item's accumulated tile
   double *wslots;      // [n_images][kSlots] partial weight sums
   unsigned long long *cslots;  // [3][kSlots] partial counters
+  // stable binning only (null otherwise): radix-sort buffers
+  uint32_t *sort_keys[2];  // [nvis] each: bin keys, ping-pong
+  uint32_t *sort_vals[2];  // [nvis] each: visibility indices, ping-pong
+  uint32_t *digit_count;   // [radix_digit_slots(nvis)] per-block digit counts, digit-major
+  uint32_t *digit_off;     // [radix_digit_slots(nvis) + 1] their exclusive scan
 };
+
+// Entries of the per-block digit count array of the stable binning's radix sort.
+int64_t radix_digit_slots(int64_t nvis);
 
 int64_t scan_temp_words(int64_t n);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
@@ -179,6 +188,10 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, u
 hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, const double *uvw,
                       const void *vis, const void *wt, const int64_t *img_off, double *wsum,
                       int64_t *counters, const BinWorkspace &W, hipStream_t s);
+
+// rows[i] = row of binned record i (row-carrying records), 0xffffffff past the last.
+hipError_t launch_plan_rows(const wproj_kernels *k, const BinShape &B, const BinWorkspace &W, int64_t nvis,
+                            uint32_t *rows, hipStream_t s);
 
 // LDS tile geometry of the tiled gridder for a handle.
 struct TileShape {

@@ -125,7 +125,7 @@ def make_kernels(params: dict, stream=None) -> Kernels:
     support_per_plane (list or None), oversample, kernel_image_size, precision
     ("f64" | "f32" | "f32_f16table"), n_images, algorithm ("tiled" | "plain"), tile, chunk,
     w_mode ("linear" | "fold" | "fold_sqrt" | "stack"), n_wlayers (w-stacking layers),
-    accumulate_runs (bool), bin_aggregate (bool)."""
+    accumulate_runs (bool), bin_aggregate (bool), stable_bins (bool)."""
     P = _lib.Params()
     P.n = int(params["n"])
     P.n_wplanes = int(params["n_wplanes"])
@@ -151,6 +151,7 @@ def make_kernels(params: dict, stream=None) -> Kernels:
     P.n_wlayers = int(params.get("n_wlayers", 0) or 0)
     P.accumulate_runs = int(bool(params.get("accumulate_runs", False)))
     P.bin_aggregate = int(bool(params.get("bin_aggregate", False)))
+    P.stable_bins = int(bool(params.get("stable_bins", False)))
     h = ctypes.c_void_p()
     _lib.check("wproj_make_kernels",
                _lib.lib().wproj_make_kernels(ctypes.byref(P), _stream(stream), ctypes.byref(h)))
@@ -311,6 +312,14 @@ class Plan:
         _lib.check("wproj_degrid_planned", _lib.lib().wproj_degrid_planned(
             self.handle, _ptr(model_grid, "model_grid", self.k.cplx, self.k.n_grids * n * n),
             _ptr(vis_out, "vis_out", self.k.cplx, self.nvis), _stream(stream)))
+
+    def rows(self, stream=None) -> torch.Tensor:
+        """wproj_plan_rows: the row of each binned record in bin order, as int32 holding
+        the uint32 rows (entries past the binned rows are 0xffffffff, i.e. -1)."""
+        out = torch.empty(self.nvis, dtype=torch.int32, device=self.workspace.device)
+        _lib.check("wproj_plan_rows", _lib.lib().wproj_plan_rows(
+            self.handle, _ptr(out, "rows", torch.int32, self.nvis), _stream(stream)))
+        return out
 
     def free(self):
         if self.handle is not None and self.handle.value:

@@ -44,6 +44,7 @@ def _params(**kw):
                                  dict(algorithm=5), dict(tile=48), dict(chunk=100),
                                  dict(w_mode=4), dict(w_mode=-1), dict(accumulate_runs=2),
                                  dict(bin_aggregate=2), dict(bin_aggregate=-1),
+                                 dict(stable_bins=2), dict(stable_bins=-1),
                                  dict(n_wlayers=2), dict(w_mode=3, n_wlayers=-1),
                                  dict(w_mode=3, n_wlayers=4097)])
 def test_make_kernels_rejects_invalid_params(bad):
@@ -72,6 +73,7 @@ def test_null_handle_paths():
     assert L.wproj_workspace_size(None, 10) == -1
     assert L.wproj_grid(None, 0, None, None, None, None, None, None, None, None, 0, None) == -1
     assert L.wproj_degrid(None, 0, None, None, None, None, None, 0, None) == -1
+    assert L.wproj_plan_rows(None, None, None) == -1
     assert L.wproj_image(None, 0, None, None, None, None, 0, None) == -1
     assert L.wproj_export(None, 0, None, 0, None, None) == -1
     assert L.wproj_footprints(None, 0, None, None, None, None) == -1
