@@ -267,15 +267,18 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
               run_record(base0, wr0, wi0, t0);
               run_record(base1, wr1, wi1, t1);
             } else {
+              // record by record (all passes of record 2i, then of 2i + 1): a cell that both
+              // footprints cover through different passes then takes its two updates in
+              // record order, as with RUNS
+              float2 t0[kPasses], t1[kPasses];
 #pragma unroll
-              for (int q = 0; q < kPasses; ++q) {
-                float2 t0, t1;
-                P::split(c[gI & 1][i][q], t0, t1);
-                if (p_on[q]) {
-                  accumulate(acc, base0 + p_off[q], wr0, wi0, t0);
-                  accumulate(acc, base1 + p_off[q], wr1, wi1, t1);
-                }
-              }
+              for (int q = 0; q < kPasses; ++q) P::split(c[gI & 1][i][q], t0[q], t1[q]);
+#pragma unroll
+              for (int q = 0; q < kPasses; ++q)
+                if (p_on[q]) accumulate(acc, base0 + p_off[q], wr0, wi0, t0[q]);
+#pragma unroll
+              for (int q = 0; q < kPasses; ++q)
+                if (p_on[q]) accumulate(acc, base1 + p_off[q], wr1, wi1, t1[q]);
             }
           }
         }

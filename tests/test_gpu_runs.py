@@ -139,3 +139,29 @@ def test_run_accumulation_planned_and_unchanged_grid():
     (Gr, _, _), _, _ = oracle_grid(base, host)
     assert rel_max(grids[1], Gr) <= TOL["f32"]
     assert rel_max(grids[1], grids[0]) <= TOL["f32"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f32_f16table"])
+@pytest.mark.parametrize("support", [3, 8, 9, 16])
+def test_run_accumulation_is_bit_identical_with_stable_bins(support, prec):
+    """With stable bins both handles see every bin's records in input order, so the
+    register-accumulating gridder, which makes the same multiply-adds in the same order,
+    gives the plain gridder's FP32 grid bit for bit (channel-major rows, where most
+    consecutive records share their origin)."""
+    wl, _, cm, _ = _channel_major_tracks()
+    uvw, vis, wt = cm
+    m = max(wl.params["kernel_image_size"], 2 * support)
+    base = {**wl.params, "support": support, "kernel_image_size": m, "precision": prec,
+            "algorithm": "tiled", "tile": 16, "chunk": 1024, "stable_bins": True}
+    u = torch.as_tensor(uvw).cuda()
+    v = torch.as_tensor(vis).to(torch.complex64).cuda()
+    w = torch.as_tensor(wt).to(torch.float32).cuda()
+    grids = []
+    for runs in (False, True):
+        k = W.make_kernels({**base, "accumulate_runs": runs})
+        g = k.new_grid()
+        W.grid(k, u, v, w, g)
+        torch.cuda.synchronize()
+        grids.append(g.clone())
+        k.free()
+    assert torch.equal(grids[0], grids[1])
