@@ -81,6 +81,10 @@ def parse():
     ap.add_argument("--degrid-only", action="store_true",
                     help="only degrid the benchmark rows --steps times (FP32 tables, --tile or 32, "
                          "chunk 8192): the command the degridder's counter runs profile")
+    ap.add_argument("--bin-only", choices=["atomic", "stable"], default=None,
+                    help="only grid the benchmark visibilities --steps times with atomic-slot or "
+                         "stable bins (FP32, --tile or 32, chunk 8192): the command the binning "
+                         "kernels' traces profile")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB device buffer 4 times (a kernel of known traffic "
                          "for scaling hardware byte counters) and exit")
@@ -112,6 +116,21 @@ def main():
         return
     if args.sweep:
         sweep(args, dev)
+        return
+    if args.bin_only:
+        wl = synth.cfg2(device=dev, precision="f32", hours=args.hours)
+        k = W.make_kernels({**wl.params, "precision": "f32", "algorithm": "tiled",
+                            "tile": args.tile or 32, "chunk": 8192,
+                            "stable_bins": args.bin_only == "stable"})
+        g = k.new_grid()
+        ws = k.workspace(wl.nvis)
+        vis32 = wl.vis.to(torch.complex64)
+        wt32 = wl.weight.to(torch.float32)
+        for _ in range(args.steps):
+            W.grid(k, wl.uvw, vis32, wt32, g, workspace=ws)
+        torch.cuda.synchronize()
+        print(json.dumps({"grid_calls": args.steps, "bins": args.bin_only, "rows": wl.nvis}), flush=True)
+        k.free()
         return
     if args.degrid_only:
         wl = synth.cfg2(device=dev, precision="f32", hours=args.hours)

@@ -205,3 +205,27 @@ def test_stable_fp32_grid_is_reproducible_bit_for_bit():
                                             w.to(torch.float64).cpu().numpy()))
     assert rel_max(first.to(torch.complex128).cpu().numpy(), Gr) <= TOL["f32"]
     k.free()
+
+
+@pytest.mark.parametrize("n", [1, 7, 4095, 4096, 4097])
+@pytest.mark.parametrize("flagged", [False, True])
+def test_stable_bins_edge_sizes(n, flagged):
+    """One radix block exactly, one row more or less, a single row, and inputs where no
+    row is gridded (every weight 0): the binned order is still the oracle's."""
+    params, uvw, vis, wt, _ = _crowded()
+    params = {**params, "precision": "f32", "stable_bins": True}
+    uvw, vis, wt = uvw[:n].copy(), vis[:n].copy(), wt[:n].copy()
+    if flagged:
+        wt[:] = 0.0
+    key = _bin_keys(params, uvw, wt, None)
+    n_in = int((key != np.iinfo(np.int64).max).sum())
+    assert n_in == (0 if flagged else n)
+    rows = _plan_rows(params, uvw, wt, None)
+    assert np.array_equal(rows[:n_in], np.argsort(key, kind="stable")[:n_in])
+    assert (rows[n_in:] == 0xFFFFFFFF).all()
+    G, sw, cnt, host = run_grid(params, uvw, vis, wt)
+    if flagged:
+        assert not np.any(G) and sw[0] == 0.0
+    else:
+        (Gr, _, _), _, _ = oracle_grid(params, host)
+        assert rel_max(G, Gr) <= TOL["f32"]
