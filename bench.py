@@ -653,10 +653,27 @@ def origin_runs(W, k, uvw, wt):
     return float(same.sum().item()) / max(int(ok.sum().item()), 1)
 
 
+def stable_origin_runs(W, params, uvw, wt):
+    """The same fraction measured exactly in bin order: stable bins, the plan's binned
+    rows (wproj_plan_rows), and each record compared with the one before it in its bin."""
+    kr = W.make_kernels({**params, "tile": 32, "chunk": 8192, "stable_bins": True})
+    plan = W.Plan(kr, uvw, wt)
+    rows = plan.rows().long()
+    fp = W.footprints(kr, uvw, wt).long()
+    n_in = int((fp[:, 5] == 0).sum().item())
+    f = fp[rows[:n_in]]
+    key = ((f[:, 1] // 32) * 1_000_003 + f[:, 0] // 32) * 4099 + f[:, 4]
+    same = (key[1:] == key[:-1]) & (f[1:, 0] == f[:-1, 0]) & (f[1:, 1] == f[:-1, 1])
+    frac = float(same.sum().item()) / max(n_in, 1)
+    plan.free()
+    kr.free()
+    return frac
+
+
 def run_accumulation(W, k, params, a1, a2, n_ant, n_ch, uvw, vis, wt, stream, reps):
     """Gridding call (binning + tile gridder + reduce) with and without accumulate_runs, on
-    the measurement-set order and on the baseline/channel/time order, and the time of the
-    reorder itself."""
+    the measurement-set order and on the baseline/channel/time order (with atomic-slot and
+    with stable bins), and the time of the reorder itself."""
     import torch
 
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -672,10 +689,15 @@ def run_accumulation(W, k, params, a1, a2, n_ant, n_ch, uvw, vis, wt, stream, re
     del perm, start, counts, vperm
     out = {"reorder_ms": reorder_ms,
            "same_origin_fraction": {"ms_order": origin_runs(W, k, uvw, wt),
-                                    "channel_major": origin_runs(W, k, uvw_c, wt_c)}}
-    for order, (u, v, w) in (("ms_order", (uvw, vis, wt)), ("channel_major", (uvw_c, vis_c, wt_c))):
+                                    "channel_major": origin_runs(W, k, uvw_c, wt_c),
+                                    "channel_major_stable": stable_origin_runs(W, params, uvw_c, wt_c)}}
+    cases = [("ms_order", (uvw, vis, wt), False), ("channel_major", (uvw_c, vis_c, wt_c), False),
+             # stable bins keep the channel-major order inside every bin
+             ("channel_major_stable", (uvw_c, vis_c, wt_c), True)]
+    for order, (u, v, w), stable in cases:
         for mode in (False, True):
-            kr = W.make_kernels({**params, "tile": 0, "chunk": 0, "accumulate_runs": mode})
+            kr = W.make_kernels({**params, "tile": 0, "chunk": 0, "accumulate_runs": mode,
+                                 "stable_bins": stable})
             ws = kr.workspace(u.shape[0])
             g = kr.new_grid()
             tune = W.autotune(kr, u, v, w, workspace=ws)
