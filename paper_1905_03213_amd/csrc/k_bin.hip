@@ -30,14 +30,16 @@ namespace {
 constexpr uint32_t kInvalid = 0xffffffffu;
 constexpr uint32_t kFoldBit = 0x80000000u;
 
-// Visibilities per thread of the key pass.  A thread issues the loads of all its
-// visibilities first and then all its count atomics before it waits on any, so a wave
-// keeps more loads and atomics in flight than with one visibility per thread.  Two
-// measured fastest: with four the key pass is no faster and the scatter after it is
-// slower (the order in which slots are handed out changes how its scattered writes
-// combine).  The scatter keeps one visibility per thread.
+// Visibilities per thread of the key pass and of the scatter.  A key-pass thread issues
+// the loads of all its visibilities first and then all its count atomics before it waits
+// on any, so a wave keeps more loads and atomics in flight than with one visibility per
+// thread.  Two measured fastest: with four the key pass is no faster and the scatter
+// after it is slower (the order in which slots are handed out changes how its scattered
+// writes combine).  The scatter, too, runs fastest with two (cfg2 binning 1.20 ms against
+// 1.24 with one and 1.28 with four).
 constexpr int kBinBlock = 256;
 constexpr int kKeyVpt = 2;
+constexpr int kScatterVpt = 2;
 
 // Runs of consecutive lanes with equal keys (rows of one baseline's channels are adjacent
 // and share tiles and planes, so a wavefront holds a few long runs).  The first lane of
@@ -451,19 +453,28 @@ __device__ inline bool make_record(const Geometry &G, const BinShape &B, int64_t
   return true;
 }
 
-// Record of visibility j to offset[key] + its slot.
+// Record of visibility j to offset[key] + its slot; kScatterVpt visibilities per thread
+// (j = block kBinBlock kScatterVpt + i kBinBlock + thread), every record built before
+// the first is stored.
 template <typename Real, typename Cplx, typename Rec, bool COMPACT>
 __global__ void __launch_bounds__(kBinBlock)
     scatter_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
                    const Cplx *__restrict__ vis, const Real *__restrict__ wt,
                    const int64_t *__restrict__ img_off, const uint32_t *__restrict__ slots,
                    const uint32_t *__restrict__ offset, int S_fix, Rec *__restrict__ rec) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nvis) return;
-  Rec r;
-  uint32_t key;
-  if (make_record<Real, Cplx, Rec, COMPACT>(G, B, nvis, uvw, vis, wt, img_off, slots, S_fix, j, r, key))
-    rec[offset[key] + slots[j]] = r;
+  Rec r[kScatterVpt];
+  uint32_t key[kScatterVpt];
+  bool ok[kScatterVpt];
+  int64_t j[kScatterVpt];
+#pragma unroll
+  for (int i = 0; i < kScatterVpt; ++i) {
+    j[i] = (int64_t)blockIdx.x * (kBinBlock * kScatterVpt) + i * kBinBlock + threadIdx.x;
+    ok[i] = j[i] < nvis &&
+            make_record<Real, Cplx, Rec, COMPACT>(G, B, nvis, uvw, vis, wt, img_off, slots, S_fix, j[i], r[i], key[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < kScatterVpt; ++i)
+    if (ok[i]) rec[offset[key[i]] + slots[j[i]]] = r[i];
 }
 
 // ---- stable binning: least-significant-digit radix sort of the bin keys ----
@@ -610,6 +621,7 @@ __global__ void __launch_bounds__(kRadixThreads)
 }
 
 // Record p (below the number of gridded visibilities, *total) from visibility order[p].
+// (Two records per thread, as in the scatter, measured slower here: 0.99 against 0.97 ms.)
 template <typename Real, typename Cplx, typename Rec, bool COMPACT>
 __global__ void __launch_bounds__(kBinBlock)
     gather_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
@@ -810,7 +822,8 @@ hipError_t place_records(const wproj_kernels *k, const BinShape &B, int64_t nvis
   const Geometry &G = k->geo;
   const dim3 grid(nblk(nvis, kBinBlock)), block(kBinBlock);
   if (!B.stable) {
-    hipLaunchKernelGGL((scatter_kernel<Real, Cplx, Rec, COMPACT>), grid, block, 0, s, G, B, nvis, uvw,
+    hipLaunchKernelGGL((scatter_kernel<Real, Cplx, Rec, COMPACT>), dim3(nblk(nvis, kBinBlock * kScatterVpt)), block,
+                       0, s, G, B, nvis, uvw,
                        (const Cplx *)vis, (const Real *)wt, img_off, W.slots, W.offset, S_fix, (Rec *)W.rec);
     return hipGetLastError();
   }
