@@ -37,8 +37,10 @@ __device__ inline float2 tap_at(const half2c *t, uint32_t i) {
 }
 
 constexpr int kDegridWaves = 4;
-// Wavefronts sharing one work item (and one tile copy) in the one-tap-per-lane degridder.
-constexpr int kTeamWaves = 4;
+// Wavefronts sharing one work item (and one tile copy) in the one-tap-per-lane degridder
+// (2048^2 benchmark rows, tile 32: 1.95 ms with one, 1.82 with four, 1.75 with eight,
+// 1.80 with sixteen).
+constexpr int kTeamWaves = 8;
 
 // (re, im) += conj(k) m as four fused multiply-adds (written out, because the compiler
 // otherwise forms a product, a fused multiply-add and an add per component)
@@ -229,8 +231,7 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
 // Fixed support S <= 8 with FP32 arithmetic and FP32 tables, packed records: the
 // gridder's layout run backwards.  A work item is taken by a team of kTeamWaves
 // wavefronts that share one tile copy, each taking every kTeamWaves-th batch of 64
-// records (a copy per wavefront would leave room for 12 wavefronts per CU at tile 32;
-// measured 1.95 -> 1.82 ms on the 2048^2 benchmark rows).  Records go in pairs, one per
+// records (a copy per wavefront would leave room for 12 wavefronts per CU at tile 32).  Records go in pairs, one per
 // half wavefront: lane
 // j of a half takes taps j and h + j (h = ceil(S^2 / 2)) of its half's record, which one
 // load from the pair-ordered table brings (entries 2j and 2j + 1 of a sub-kernel), and
