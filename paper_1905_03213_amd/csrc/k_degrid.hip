@@ -1,10 +1,11 @@
 // Tiled degridder (the gather that is the adjoint of gridding):
 //   V_j = sum_{kv,ku} conj(T_p[ov][ou][kv][ku]) M[y0+kv][x0+ku].
 // Visibilities are binned by (image, uv-tile, w-plane) exactly as for gridding, but each
-// record carries its visibility's row instead of W V.  A wavefront takes one work item
+// record carries its visibility's row instead of W V.  A workgroup takes one work item
 // (a run of records of one tile), copies that tile of the model grid plus its
-// (S_max - 1)-cell halo into its private LDS with coalesced row loads, and then serves
-// every record's footprint from LDS instead of gathering it from HBM.
+// (S_max - 1)-cell halo into LDS with coalesced row loads, and then serves every
+// record's footprint from LDS instead of gathering it from HBM.  The copy is only read,
+// so the workgroup's wavefronts share it and split the item's records between them.
 //
 // Two kernels serve the records.  With FP32 arithmetic and tables and a fixed support
 // up to 8, tap_lane_degrid_kernel (below) gives each lane one tap of a record, as the
@@ -36,7 +37,10 @@ __device__ inline float2 tap_at(const half2c *t, uint32_t i) {
   return make_float2((float)h.re, (float)h.im);
 }
 
-constexpr int kDegridWaves = 4;
+// Wavefronts sharing one work item (and one tile copy) in the row-per-lane degridder
+// (2048^2 benchmark rows, tile 32, FP16 tables: 1.58 ms with a copy per wavefront, 1.44
+// with four per copy, 1.34 with eight, 1.37 with sixteen; FP64 7.06 -> 6.65 ms).
+constexpr int kDegridWaves = 8;
 // Wavefronts sharing one work item (and one tile copy) in the one-tap-per-lane degridder
 // (2048^2 benchmark rows, tile 32: 1.95 ms with one, 1.82 with four, 1.75 with eight,
 // 1.80 with sixteen).
@@ -86,9 +90,10 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
                         typename Cd<Real>::T *__restrict__ out) {
   using C2 = typename Cd<Real>::T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ uint32_t s_item;
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  C2 *tile = reinterpret_cast<C2 *>(smem_raw) + (size_t)wid * wave_lds;
+  C2 *tile = reinterpret_cast<C2 *>(smem_raw);  // one copy for the workgroup's wavefronts
   const int grp = lane >> 3, r = lane & 7;
   const uint32_t n_items = *n_items_ptr;
   const int64_t cells = (int64_t)G.n * G.n;
@@ -96,9 +101,10 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
   const bool folding = G.w_mode != WPROJ_W_LINEAR;
 
   for (;;) {
-    uint32_t got = 0;
-    if (lane == 0) got = atomicAdd(counter, 1u);
-    const uint32_t it = (uint32_t)__builtin_amdgcn_readlane((int)got, 0);
+    __syncthreads();  // every wave is done with the previous tile and item
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t it = s_item;
     if (it >= n_items) break;
     const WorkItem w = items[order[it]];  // largest items first
     const int img = (int)(w.tile / (uint32_t)tiles_per_img);
@@ -106,11 +112,7 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
     const int ty = rt / B.ntx, tx = rt - ty * B.ntx;
     const int ox = tx * B.tile, oy = ty * B.tile;
     const C2 *mimg = model + cells * img;
-    // this wavefront's earlier reads of the previous tile precede these writes: LDS
-    // executes one wavefront's instructions in order; the barrier keeps the compiler
-    // from moving accesses across
-    __builtin_amdgcn_wave_barrier();
-    for (int i = lane; i < rows * rows; i += 64) {
+    for (int i = threadIdx.x; i < rows * rows; i += blockDim.x) {
       const int ry = i / rows, rx = i - ry * rows;
       const int gy = oy + ry, gx = ox + rx;
       C2 v;
@@ -119,7 +121,7 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
       if (gy < G.n && gx < G.n) v = mimg[(int64_t)gy * G.n + gx];
       tile[ry * pitch + rx] = v;
     }
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
 
     if constexpr (S > 0 && S <= 8) {
       // Fixed support: records arrive 64 at a time in one coalesced load (lane i holds
@@ -149,12 +151,14 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
           tap_row[ku].y = k.y;
         }
       };
+      // wavefront wid takes batches wid, wid + kDegridWaves, ...
+      constexpr uint32_t kStep = 64u * kDegridWaves;
       Rec cur;
-      if (n_rec > 0) load_batch(0, cur);
-      for (uint32_t b = 0; b < n_rec; b += 64) {
+      if ((uint32_t)wid * 64u < n_rec) load_batch((uint32_t)wid * 64u, cur);
+      for (uint32_t b = (uint32_t)wid * 64u; b < n_rec; b += kStep) {
         Rec nxt;
-        const bool more = b + 64 < n_rec;
-        if (more) load_batch(b + 64, nxt);
+        const bool more = b + kStep < n_rec;
+        if (more) load_batch(b + kStep, nxt);
         // taps are loaded kAhead steps ahead: one with FP32/FP64 tables, two with FP16
         // tables, whose half-size loads leave registers and bandwidth for the deeper
         // prefetch (measured: FP16 1.66 -> 1.57 ms on the 2048^2 benchmark rows; FP32 got
@@ -196,7 +200,7 @@ __global__ void __launch_bounds__(64 * kDegridWaves)
         if (more) cur = nxt;
       }
     } else {
-      for (uint32_t b = w.begin; b < w.end; b += 8) {
+      for (uint32_t b = w.begin + (uint32_t)wid * 8u; b < w.end; b += 8u * kDegridWaves) {
         const uint32_t jr = b + (uint32_t)grp;
         const bool valid = jr < w.end;
         const Rec rr = rec[valid ? jr : w.begin];
@@ -459,8 +463,8 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
                       const BinWorkspace &W, const void *model, void *out, hipStream_t s) {
   using C2 = typename Cd<Real>::T;
   auto kern = tiled_degrid_kernel<Real, Rec, Tab, S>;
-  const int wpb = (int)std::max<size_t>(1, std::min<size_t>(kDegridWaves, k->max_lds / ts.lds_bytes));
-  const size_t lds = ts.lds_bytes * wpb;
+  const int wpb = kDegridWaves;
+  const size_t lds = ts.lds_bytes;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
