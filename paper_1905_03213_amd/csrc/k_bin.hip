@@ -30,16 +30,17 @@ namespace {
 constexpr uint32_t kInvalid = 0xffffffffu;
 constexpr uint32_t kFoldBit = 0x80000000u;
 
-// Visibilities per thread of the key pass and of the scatter.  A key-pass thread issues
-// the loads of all its visibilities first and then all its count atomics before it waits
-// on any, so a wave keeps more loads and atomics in flight than with one visibility per
-// thread.  Two measured fastest: with four the key pass is no faster and the scatter
-// after it is slower (the order in which slots are handed out changes how its scattered
-// writes combine).  The scatter, too, runs fastest with two (cfg2 binning 1.20 ms against
-// 1.24 with one and 1.28 with four).
+// Visibilities per thread of the key pass.  A key-pass thread issues the loads of all its
+// visibilities first and then all its count atomics before it waits on any, so a wave
+// keeps more loads and atomics in flight than with one visibility per thread.  Two
+// measured fastest: with four the key pass is no faster and the scatter after it is
+// slower (the order in which slots are handed out changes how its scattered writes
+// combine).  The scatter takes two per thread after the per-wavefront-run key pass with
+// compact records (cfg2 binning 1.20 ms against 1.24 with one and 1.28 with four), one
+// otherwise (two measured slower: +0.07 ms on cfg3's recomputed records, +0.06 ms after
+// cfg4's aggregated key pass).
 constexpr int kBinBlock = 256;
 constexpr int kKeyVpt = 2;
-constexpr int kScatterVpt = 2;
 
 // Runs of consecutive lanes with equal keys (rows of one baseline's channels are adjacent
 // and share tiles and planes, so a wavefront holds a few long runs).  The first lane of
@@ -453,27 +454,27 @@ __device__ inline bool make_record(const Geometry &G, const BinShape &B, int64_t
   return true;
 }
 
-// Record of visibility j to offset[key] + its slot; kScatterVpt visibilities per thread
-// (j = block kBinBlock kScatterVpt + i kBinBlock + thread), every record built before
-// the first is stored.
-template <typename Real, typename Cplx, typename Rec, bool COMPACT>
+// Record of visibility j to offset[key] + its slot; V visibilities per thread
+// (j = block kBinBlock V + i kBinBlock + thread), every record built before the first is
+// stored.
+template <typename Real, typename Cplx, typename Rec, bool COMPACT, int V>
 __global__ void __launch_bounds__(kBinBlock)
     scatter_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
                    const Cplx *__restrict__ vis, const Real *__restrict__ wt,
                    const int64_t *__restrict__ img_off, const uint32_t *__restrict__ slots,
                    const uint32_t *__restrict__ offset, int S_fix, Rec *__restrict__ rec) {
-  Rec r[kScatterVpt];
-  uint32_t key[kScatterVpt];
-  bool ok[kScatterVpt];
-  int64_t j[kScatterVpt];
+  Rec r[V];
+  uint32_t key[V];
+  bool ok[V];
+  int64_t j[V];
 #pragma unroll
-  for (int i = 0; i < kScatterVpt; ++i) {
-    j[i] = (int64_t)blockIdx.x * (kBinBlock * kScatterVpt) + i * kBinBlock + threadIdx.x;
+  for (int i = 0; i < V; ++i) {
+    j[i] = (int64_t)blockIdx.x * (kBinBlock * V) + i * kBinBlock + threadIdx.x;
     ok[i] = j[i] < nvis &&
             make_record<Real, Cplx, Rec, COMPACT>(G, B, nvis, uvw, vis, wt, img_off, slots, S_fix, j[i], r[i], key[i]);
   }
 #pragma unroll
-  for (int i = 0; i < kScatterVpt; ++i)
+  for (int i = 0; i < V; ++i)
     if (ok[i]) rec[offset[key[i]] + slots[j[i]]] = r[i];
 }
 
@@ -621,7 +622,7 @@ __global__ void __launch_bounds__(kRadixThreads)
 }
 
 // Record p (below the number of gridded visibilities, *total) from visibility order[p].
-// (Two records per thread, as in the scatter, measured slower here: 0.99 against 0.97 ms.)
+// (Two records per thread measured slower here: 0.99 against 0.97 ms.)
 template <typename Real, typename Cplx, typename Rec, bool COMPACT>
 __global__ void __launch_bounds__(kBinBlock)
     gather_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
@@ -822,9 +823,13 @@ hipError_t place_records(const wproj_kernels *k, const BinShape &B, int64_t nvis
   const Geometry &G = k->geo;
   const dim3 grid(nblk(nvis, kBinBlock)), block(kBinBlock);
   if (!B.stable) {
-    hipLaunchKernelGGL((scatter_kernel<Real, Cplx, Rec, COMPACT>), dim3(nblk(nvis, kBinBlock * kScatterVpt)), block,
-                       0, s, G, B, nvis, uvw,
-                       (const Cplx *)vis, (const Real *)wt, img_off, W.slots, W.offset, S_fix, (Rec *)W.rec);
+    if (COMPACT && !B.aggregate)
+      hipLaunchKernelGGL((scatter_kernel<Real, Cplx, Rec, COMPACT, 2>), dim3(nblk(nvis, 2 * kBinBlock)), block, 0, s,
+                         G, B, nvis, uvw, (const Cplx *)vis, (const Real *)wt, img_off, W.slots, W.offset, S_fix,
+                         (Rec *)W.rec);
+    else
+      hipLaunchKernelGGL((scatter_kernel<Real, Cplx, Rec, COMPACT, 1>), grid, block, 0, s, G, B, nvis, uvw,
+                         (const Cplx *)vis, (const Real *)wt, img_off, W.slots, W.offset, S_fix, (Rec *)W.rec);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((sort_key_kernel<Real, COMPACT>), grid, block, 0, s, G, B, nvis, uvw, (const Real *)wt,
