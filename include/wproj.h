@@ -124,7 +124,7 @@ typedef struct {
                                and results either way).  0: the first lane of each run of
                                equal bins in a wavefront adds the run with one global atomic,
                                which suits rows in measurement-set order (a row's channels
-                               share bins).  1: blocks of 4096 visibilities first add their
+                               share bins).  1: blocks of 2048 visibilities first add their
                                counts in an LDS hash table, then take one global atomic per
                                distinct bin, which suits rows whose equal bins lie hundreds of
                                rows apart (one channel per row in time order: the same

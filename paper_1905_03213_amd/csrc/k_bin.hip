@@ -244,15 +244,18 @@ __global__ void __launch_bounds__(kBinBlock)
 // choice is the handle's (BinShape::aggregate, which wproj_autotune times).  A run whose
 // key finds no entry within kAggProbes probes takes a global atomic of its own.  Same
 // outputs as key_kernel.
-constexpr int kAggThreads = 1024;
+// Shape measured on cfg4's rows (bin phase): 512 threads x 4 visibilities 1.38 ms, 1024 x 4
+// 1.48, 1024 x 2 1.61, 1024 x 8 1.46, 512 x 8 1.39, 256 x 8 1.46; 2048 or 4096 table
+// entries alike.
+constexpr int kAggThreads = 512;
 constexpr int kAggVpt = 4;
 constexpr int kAggSpan = kAggThreads * kAggVpt;
-constexpr int kAggSlots = 4096;  // a power of two
+constexpr int kAggSlots = 2048;  // a power of two
 constexpr int kAggProbes = 16;
 constexpr uint32_t kDirect = 0xffffffffu;  // entry index of a run counted globally
 
-__device__ inline uint32_t agg_hash(uint32_t key) { return (key * 2654435761u) >> (32 - 12); }
-static_assert(kAggSlots == 1 << 12, "agg_hash yields 12 bits");
+__device__ inline uint32_t agg_hash(uint32_t key) { return (key * 2654435761u) >> (32 - 11); }
+static_assert(kAggSlots == 1 << 11, "agg_hash yields 11 bits");
 
 template <typename Real, bool COMPACT>
 __global__ void __launch_bounds__(kAggThreads)

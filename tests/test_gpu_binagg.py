@@ -50,9 +50,10 @@ def test_aggregated_binning_matches_oracle(which, prec):
 
 
 def test_aggregated_binning_crowded_table():
-    """4096 visibilities per block spread over 2048^2 cells (16-cell tiles) and 64
-    planes: nearly every run has a bin of its own, more than the table can place within
-    its probe limit, so some runs take global atomics of their own."""
+    """2048 visibilities per block spread over 2048^2 cells (16-cell tiles) and 64
+    planes: nearly every run has a bin of its own, as many as the table has entries, more
+    than linear probing places within its probe limit, so some runs take global atomics
+    of their own."""
     rng = np.random.default_rng(21)
     n, cell = 2048, 1e-5
     params = dict(n=n, cell_rad=cell, n_wplanes=64, w_max=500.0, support=8, oversample=8,
