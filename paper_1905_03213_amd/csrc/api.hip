@@ -255,8 +255,9 @@ int64_t carve(const wproj_kernels *k, int64_t nvis, char *base, BinWorkspace &W)
     off += align_up(bytes);
     return p;
   };
-  // slot per visibility; with packed records also its key and the record's first word
-  W.slots = (uint32_t *)take(4 * nvis * (B.pack_sub ? 3 : 1));
+  // per visibility: slot, key and the record's first word; with per-plane supports also
+  // the record's tap word
+  W.slots = (uint32_t *)take(4 * nvis * (B.pack_sub ? 3 : 4));
   W.rec = take(rec_bytes * nvis);
   W.count = (uint32_t *)take(4 * B.n_keys);
   W.offset = (uint32_t *)take(4 * (B.n_keys + 1));

@@ -15,12 +15,13 @@
 // record's place inside its bin follows the order in which the runs' atomics land (the
 // bin's contents are fixed, their order is not).  Stable bins (BinShape::stable) replace
 // the scatter by a stable radix sort of the keys and a gather in sorted order, so that a
-// bin keeps its visibilities in input order.  With a fixed support (records carry
-// the packed LDS offset and sub-kernel number) the key pass also stores each
-// visibility's key and packed word next to its slot, so the scatter reads 12 bytes
-// instead of the 24-byte uvw and skips the FP64 footprint; otherwise the scatter
-// computes the footprint again from the coordinates.
+// bin keeps its visibilities in input order.  The key pass also stores each
+// visibility's key and its record's first word (the LDS offset, with the sub-kernel
+// number above it for a fixed support) next to its slot, and with per-plane supports the
+// record's tap word too, so the scatter reads 12 or 16 bytes instead of the 24-byte uvw
+// and never computes a footprint again.
 #include <algorithm>
+#include <type_traits>
 
 #include "wproj_tiled.h"
 
@@ -36,9 +37,10 @@ constexpr uint32_t kFoldBit = 0x80000000u;
 // measured fastest: with four the key pass is no faster and the scatter after it is
 // slower (the order in which slots are handed out changes how its scattered writes
 // combine).  The scatter takes two per thread after the per-wavefront-run key pass with
-// compact records (cfg2 binning 1.20 ms against 1.24 with one and 1.28 with four), one
-// otherwise (two measured slower: +0.07 ms on cfg3's recomputed records, +0.06 ms after
-// cfg4's aggregated key pass).
+// packed records of a fixed support (cfg2 binning 1.20 ms against 1.24 with one and 1.28
+// with four), one otherwise (two measured slower: +0.06 ms after cfg4's aggregated key
+// pass, and +0.07 ms on cfg3's per-plane supports while the scatter still computed their
+// footprints again).
 constexpr int kBinBlock = 256;
 constexpr int kKeyVpt = 2;
 
@@ -92,6 +94,12 @@ __device__ inline uint32_t record_lds(const Geometry &G, const BinShape &B, cons
   return r;
 }
 
+// A record's tap word: its sub-kernel's first tap, with S - 1 above it.
+__device__ inline uint32_t tap_word(const Geometry &G, const Footprint &f) {
+  const int S = G.supp[f.p];
+  return (uint32_t)(G.tab_off[f.p] + (uint32_t)((f.ov * G.O + f.ou) * S * S)) | ((uint32_t)(S - 1) << kTapBits);
+}
+
 // Image of every row of the block when one image holds them all (images are contiguous
 // row ranges), else -1; first receives the image of the block's first row (-1 when it
 // is in none).  The arguments are the same in every lane.
@@ -114,10 +122,12 @@ __device__ inline int64_t bin_row(int i) {
   return (int64_t)blockIdx.x * (kBinBlock * VPT) + i * kBinBlock + threadIdx.x;
 }
 
-// COMPACT: slots holds three arrays of nvis words: slot, key (kInvalid when the
-// visibility is not gridded; a Hermitian-folded visibility has the key's top bit set,
-// keys then stay below 2^31) and the record's packed first word.  Otherwise only the slot.
-template <typename Real, bool COMPACT>
+// slots holds arrays of nvis words: slot, key (kInvalid when the visibility is not
+// gridded; a Hermitian-folded visibility has the key's top bit set, keys stay below
+// 2^31), the record's first word and, with TAPWORD (per-plane supports, records that
+// carry their first tap), the record's tap word.  A fixed support S_fix packs the
+// sub-kernel number into the first word instead.
+template <typename Real, bool TAPWORD>
 __global__ void __launch_bounds__(kBinBlock)
     key_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
                const Real *__restrict__ wt, const int64_t *__restrict__ img_off,
@@ -142,7 +152,7 @@ __global__ void __launch_bounds__(kBinBlock)
   int img_b;  // image of the block's first row
   const int img_all = block_image<V>(img_off, G.n_images, nvis, img_b);
   // then every footprint (kernel-table lookups included) ...
-  uint32_t key[V], packed[V];
+  uint32_t key[V], packed[V], tapw[V];
   bool fold[V];
   double w_mine = 0.0;
   unsigned n_drop = 0, n_clamp = 0, n_bad = 0;
@@ -151,6 +161,7 @@ __global__ void __launch_bounds__(kBinBlock)
     const int64_t j = bin_row<V>(i);
     key[i] = kInvalid;
     packed[i] = 0;
+    tapw[i] = 0;
     fold[i] = false;
     int cls = kFlagged;
     bool clamped = false;
@@ -158,11 +169,12 @@ __global__ void __launch_bounds__(kBinBlock)
       const int img = img_all >= 0 ? img_all : image_of(img_off, G.n_images, j);
       if (img >= 0) {
         Footprint f;
-        cls = classify(G, c[i], wj[i], f, COMPACT ? S_fix : 0);
+        cls = classify(G, c[i], wj[i], f, TAPWORD ? 0 : S_fix);
         if (cls == kGridded) {
           key[i] = bin_key(G, B, img, f);
           fold[i] = f.fold;
-          if constexpr (COMPACT) packed[i] = record_lds(G, B, f);
+          packed[i] = record_lds(G, B, f);
+          if constexpr (TAPWORD) tapw[i] = tap_word(G, f);
           clamped = w_clamped(G, c[i][2]);
           // rows of an image other than the block's first row's image (only in blocks
           // that straddle an image boundary) add their weights to their image's slot
@@ -193,10 +205,9 @@ __global__ void __launch_bounds__(kBinBlock)
     const uint32_t slot = __shfl(got[i], run[i].leader, 64) + (uint32_t)((threadIdx.x & 63) - run[i].leader);
     if (j < nvis) {
       slots[j] = slot;
-      if constexpr (COMPACT) {
-        slots[nvis + j] = fold[i] ? (key[i] | kFoldBit) : key[i];
-        slots[2 * nvis + j] = packed[i];
-      }
+      slots[nvis + j] = fold[i] ? (key[i] | kFoldBit) : key[i];
+      slots[2 * nvis + j] = packed[i];
+      if constexpr (TAPWORD) slots[3 * nvis + j] = tapw[i];
     }
   }
   // Counters and weight sums: reduced over the workgroup in LDS, then one atomic per
@@ -257,7 +268,7 @@ constexpr uint32_t kDirect = 0xffffffffu;  // entry index of a run counted globa
 __device__ inline uint32_t agg_hash(uint32_t key) { return (key * 2654435761u) >> (32 - 11); }
 static_assert(kAggSlots == 1 << 11, "agg_hash yields 11 bits");
 
-template <typename Real, bool COMPACT>
+template <typename Real, bool TAPWORD>
 __global__ void __launch_bounds__(kAggThreads)
     key_agg_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
                    const Real *__restrict__ wt, const int64_t *__restrict__ img_off,
@@ -293,7 +304,7 @@ __global__ void __launch_bounds__(kAggThreads)
     const int last = image_of(img_off, G.n_images, min(j_first + (int64_t)kAggSpan, nvis) - 1);
     img_all = img_b >= 0 && img_b == last ? img_b : -1;
   }
-  uint32_t key[V], packed[V];
+  uint32_t key[V], packed[V], tapw[V];
   bool fold[V];
   double w_mine = 0.0;
   unsigned n_drop = 0, n_clamp = 0, n_bad = 0;
@@ -302,6 +313,7 @@ __global__ void __launch_bounds__(kAggThreads)
     const int64_t j = row(i);
     key[i] = kInvalid;
     packed[i] = 0;
+    tapw[i] = 0;
     fold[i] = false;
     int cls = kFlagged;
     bool clamped = false;
@@ -309,11 +321,12 @@ __global__ void __launch_bounds__(kAggThreads)
       const int img = img_all >= 0 ? img_all : image_of(img_off, G.n_images, j);
       if (img >= 0) {
         Footprint f;
-        cls = classify(G, c[i], wj[i], f, COMPACT ? S_fix : 0);
+        cls = classify(G, c[i], wj[i], f, TAPWORD ? 0 : S_fix);
         if (cls == kGridded) {
           key[i] = bin_key(G, B, img, f);
           fold[i] = f.fold;
-          if constexpr (COMPACT) packed[i] = record_lds(G, B, f);
+          packed[i] = record_lds(G, B, f);
+          if constexpr (TAPWORD) tapw[i] = tap_word(G, f);
           clamped = w_clamped(G, c[i][2]);
           if (img == img_b)
             w_mine += (double)wj[i];
@@ -372,10 +385,9 @@ __global__ void __launch_bounds__(kAggThreads)
                           (uint32_t)((threadIdx.x & 63) - run[i].leader);
     if (j < nvis) {
       slots[j] = slot;
-      if constexpr (COMPACT) {
-        slots[nvis + j] = fold[i] ? (key[i] | kFoldBit) : key[i];
-        slots[2 * nvis + j] = packed[i];
-      }
+      slots[nvis + j] = fold[i] ? (key[i] | kFoldBit) : key[i];
+      slots[2 * nvis + j] = packed[i];
+      if constexpr (TAPWORD) slots[3 * nvis + j] = tapw[i];
     }
   }
   // counters and weight sums, as in key_kernel
@@ -409,40 +421,25 @@ __global__ void __launch_bounds__(kAggThreads)
   }
 }
 
-// The record of visibility j and its bin key; false when j is not gridded.  COMPACT: the
-// key pass stored each visibility's key and packed first word (fixed support S_fix, whose
-// sub-kernel number n starts at tap n S_fix^2); otherwise the footprint is computed again
-// from the same inputs, with the same outcome.  The key is loaded first, so that the bin
-// offset it indexes is fetched while the rest of the record's inputs arrive; rows that
-// are not gridded load nothing more.
-template <typename Real, typename Cplx, typename Rec, bool COMPACT>
-__device__ inline bool make_record(const Geometry &G, const BinShape &B, int64_t nvis,
-                                   const double *__restrict__ uvw, const Cplx *__restrict__ vis,
-                                   const Real *__restrict__ wt, const int64_t *__restrict__ img_off,
+// The record of visibility j and its bin key, from what the key pass stored; false when
+// j is not gridded.  The key is loaded first, so that the bin offset it indexes is
+// fetched while the rest of the record's inputs arrive; rows that are not gridded load
+// nothing more.  TAPWORD: the tap word was stored; otherwise the first tap is the packed
+// sub-kernel number times S_fix^2.
+template <typename Real, typename Cplx, typename Rec, bool TAPWORD>
+__device__ inline bool make_record(int64_t nvis, const Cplx *__restrict__ vis, const Real *__restrict__ wt,
                                    const uint32_t *__restrict__ slots, int S_fix, int64_t j, Rec &r,
                                    uint32_t &key) {
-  bool fold;
-  if constexpr (COMPACT) {
-    key = slots[nvis + j];
-    if (key == kInvalid) return false;
-    fold = (key & kFoldBit) != 0;
-    key &= ~kFoldBit;
-    r.lds = slots[2 * nvis + j];
-    if constexpr (kHasTap<Rec>)
+  key = slots[nvis + j];
+  if (key == kInvalid) return false;
+  const bool fold = (key & kFoldBit) != 0;
+  key &= ~kFoldBit;
+  r.lds = slots[2 * nvis + j];
+  if constexpr (kHasTap<Rec>) {
+    if constexpr (TAPWORD)
+      r.tap = slots[3 * nvis + j];
+    else
       r.tap = (r.lds >> kLdsBits) * (uint32_t)(S_fix * S_fix) | ((uint32_t)(S_fix - 1) << kTapBits);
-  } else {
-    const int img = image_of(img_off, G.n_images, j);
-    if (img < 0) return false;
-    Footprint f;
-    const Real w = wt ? wt[j] : Real(1);
-    if (classify(G, uvw + 3 * j, w, f) != kGridded) return false;
-    fold = f.fold;
-    key = bin_key(G, B, img, f);
-    const int S = G.supp[f.p];
-    r.lds = record_lds(G, B, f);
-    if constexpr (kHasTap<Rec>)
-      r.tap = (uint32_t)(G.tab_off[f.p] + (uint32_t)((f.ov * G.O + f.ou) * S * S)) |
-              ((uint32_t)(S - 1) << kTapBits);
   }
   const Real w = wt ? wt[j] : Real(1);
   if (vis) {
@@ -460,12 +457,11 @@ __device__ inline bool make_record(const Geometry &G, const BinShape &B, int64_t
 // Record of visibility j to offset[key] + its slot; V visibilities per thread
 // (j = block kBinBlock V + i kBinBlock + thread), every record built before the first is
 // stored.
-template <typename Real, typename Cplx, typename Rec, bool COMPACT, int V>
+template <typename Real, typename Cplx, typename Rec, bool TAPWORD, int V>
 __global__ void __launch_bounds__(kBinBlock)
-    scatter_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
-                   const Cplx *__restrict__ vis, const Real *__restrict__ wt,
-                   const int64_t *__restrict__ img_off, const uint32_t *__restrict__ slots,
-                   const uint32_t *__restrict__ offset, int S_fix, Rec *__restrict__ rec) {
+    scatter_kernel(int64_t nvis, const Cplx *__restrict__ vis, const Real *__restrict__ wt,
+                   const uint32_t *__restrict__ slots, const uint32_t *__restrict__ offset, int S_fix,
+                   Rec *__restrict__ rec) {
   Rec r[V];
   uint32_t key[V];
   bool ok[V];
@@ -474,7 +470,7 @@ __global__ void __launch_bounds__(kBinBlock)
   for (int i = 0; i < V; ++i) {
     j[i] = (int64_t)blockIdx.x * (kBinBlock * V) + i * kBinBlock + threadIdx.x;
     ok[i] = j[i] < nvis &&
-            make_record<Real, Cplx, Rec, COMPACT>(G, B, nvis, uvw, vis, wt, img_off, slots, S_fix, j[i], r[i], key[i]);
+            make_record<Real, Cplx, Rec, TAPWORD>(nvis, vis, wt, slots, S_fix, j[i], r[i], key[i]);
   }
 #pragma unroll
   for (int i = 0; i < V; ++i)
@@ -523,26 +519,13 @@ __device__ inline int64_t radix_elem(int w, int i, int lane) {
   return (int64_t)blockIdx.x * kRadixTile + (int64_t)w * (64 * kRadixSteps) + i * 64 + lane;
 }
 
-template <typename Real, bool COMPACT>
 __global__ void __launch_bounds__(kBinBlock)
-    sort_key_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
-                    const Real *__restrict__ wt, const int64_t *__restrict__ img_off,
-                    const uint32_t *__restrict__ slots, uint32_t *__restrict__ keys) {
+    sort_key_kernel(int64_t nvis, uint32_t n_keys, const uint32_t *__restrict__ slots,
+                    uint32_t *__restrict__ keys) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nvis) return;
-  uint32_t key = (uint32_t)B.n_keys;
-  if constexpr (COMPACT) {
-    const uint32_t kw = slots[nvis + j];
-    if (kw != kInvalid) key = kw & ~kFoldBit;
-  } else {
-    const int img = image_of(img_off, G.n_images, j);
-    if (img >= 0) {
-      Footprint f;
-      const Real w = wt ? wt[j] : Real(1);
-      if (classify(G, uvw + 3 * j, w, f) == kGridded) key = bin_key(G, B, img, f);
-    }
-  }
-  keys[j] = key;
+  const uint32_t kw = slots[nvis + j];
+  keys[j] = kw != kInvalid ? kw & ~kFoldBit : n_keys;
 }
 
 // count[d * n_blocks + block] = elements of the block whose digit is d.
@@ -626,19 +609,16 @@ __global__ void __launch_bounds__(kRadixThreads)
 
 // Record p (below the number of gridded visibilities, *total) from visibility order[p].
 // (Two records per thread measured slower here: 0.99 against 0.97 ms.)
-template <typename Real, typename Cplx, typename Rec, bool COMPACT>
+template <typename Real, typename Cplx, typename Rec, bool TAPWORD>
 __global__ void __launch_bounds__(kBinBlock)
-    gather_kernel(Geometry G, BinShape B, int64_t nvis, const double *__restrict__ uvw,
-                  const Cplx *__restrict__ vis, const Real *__restrict__ wt,
-                  const int64_t *__restrict__ img_off, const uint32_t *__restrict__ slots,
-                  const uint32_t *__restrict__ order, const uint32_t *__restrict__ total, int S_fix,
-                  Rec *__restrict__ rec) {
+    gather_kernel(int64_t nvis, const Cplx *__restrict__ vis, const Real *__restrict__ wt,
+                  const uint32_t *__restrict__ slots, const uint32_t *__restrict__ order,
+                  const uint32_t *__restrict__ total, int S_fix, Rec *__restrict__ rec) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= (int64_t)*total) return;
   Rec r;
   uint32_t key;
-  if (make_record<Real, Cplx, Rec, COMPACT>(G, B, nvis, uvw, vis, wt, img_off, slots, S_fix,
-                                            (int64_t)order[p], r, key))
+  if (make_record<Real, Cplx, Rec, TAPWORD>(nvis, vis, wt, slots, S_fix, (int64_t)order[p], r, key))
     rec[p] = r;
 }
 
@@ -819,24 +799,20 @@ inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 
 // Records in bin order: scattered to offset[key] + slot, or, for stable bins, sorted by
 // key (radix passes over the key's significant bits) and gathered in sorted order.
-template <typename Real, typename Cplx, typename Rec, bool COMPACT>
-hipError_t place_records(const wproj_kernels *k, const BinShape &B, int64_t nvis, const double *uvw,
-                         const void *vis, const void *wt, const int64_t *img_off, const BinWorkspace &W,
-                         int S_fix, hipStream_t s) {
-  const Geometry &G = k->geo;
+template <typename Real, typename Cplx, typename Rec, bool TAPWORD>
+hipError_t place_records(const wproj_kernels *k, const BinShape &B, int64_t nvis, const void *vis, const void *wt,
+                         const BinWorkspace &W, int S_fix, hipStream_t s) {
   const dim3 grid(nblk(nvis, kBinBlock)), block(kBinBlock);
   if (!B.stable) {
-    if (COMPACT && !B.aggregate)
-      hipLaunchKernelGGL((scatter_kernel<Real, Cplx, Rec, COMPACT, 2>), dim3(nblk(nvis, 2 * kBinBlock)), block, 0, s,
-                         G, B, nvis, uvw, (const Cplx *)vis, (const Real *)wt, img_off, W.slots, W.offset, S_fix,
-                         (Rec *)W.rec);
+    if (!TAPWORD && !B.aggregate)
+      hipLaunchKernelGGL((scatter_kernel<Real, Cplx, Rec, TAPWORD, 2>), dim3(nblk(nvis, 2 * kBinBlock)), block, 0, s,
+                         nvis, (const Cplx *)vis, (const Real *)wt, W.slots, W.offset, S_fix, (Rec *)W.rec);
     else
-      hipLaunchKernelGGL((scatter_kernel<Real, Cplx, Rec, COMPACT, 1>), grid, block, 0, s, G, B, nvis, uvw,
-                         (const Cplx *)vis, (const Real *)wt, img_off, W.slots, W.offset, S_fix, (Rec *)W.rec);
+      hipLaunchKernelGGL((scatter_kernel<Real, Cplx, Rec, TAPWORD, 1>), grid, block, 0, s, nvis, (const Cplx *)vis,
+                         (const Real *)wt, W.slots, W.offset, S_fix, (Rec *)W.rec);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL((sort_key_kernel<Real, COMPACT>), grid, block, 0, s, G, B, nvis, uvw, (const Real *)wt,
-                     img_off, W.slots, W.sort_keys[0]);
+  hipLaunchKernelGGL(sort_key_kernel, grid, block, 0, s, nvis, (uint32_t)B.n_keys, W.slots, W.sort_keys[0]);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // keys run from 0 to n_keys (not gridded)
@@ -859,9 +835,8 @@ hipError_t place_records(const wproj_kernels *k, const BinShape &B, int64_t nvis
     vals = W.sort_vals[cur ^ 1];
     cur ^= 1;
   }
-  hipLaunchKernelGGL((gather_kernel<Real, Cplx, Rec, COMPACT>), grid, block, 0, s, G, B, nvis, uvw,
-                     (const Cplx *)vis, (const Real *)wt, img_off, W.slots, vals, W.offset + B.n_keys, S_fix,
-                     (Rec *)W.rec);
+  hipLaunchKernelGGL((gather_kernel<Real, Cplx, Rec, TAPWORD>), grid, block, 0, s, nvis, (const Cplx *)vis,
+                     (const Real *)wt, W.slots, vals, W.offset + B.n_keys, S_fix, (Rec *)W.rec);
   return hipGetLastError();
 }
 
@@ -918,38 +893,30 @@ hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, c
   const dim3 key_grid(nblk(nvis, kBinBlock * kKeyVpt)), block(kBinBlock);
   const bool agg = B.aggregate != 0;  // counts aggregated per block in LDS
   const dim3 agg_grid(nblk(nvis, kAggSpan)), agg_block(kAggThreads);
-  const bool compact = B.pack_sub != 0;
+  // per-plane supports: the key pass stores each record's tap word (TAPWORD); a fixed
+  // support packs the sub-kernel number into the record's first word instead
+  const bool tapword = B.pack_sub == 0;
   const int S_fix = k->s_max;  // the fixed support of packed records
+  auto key_pass = [&](auto real_tag, auto tap_tag) {
+    using Real = decltype(real_tag);
+    constexpr bool TW = decltype(tap_tag)::value;
+    if (agg)
+      hipLaunchKernelGGL((key_agg_kernel<Real, TW>), agg_grid, agg_block, 0, s, G, B, nvis, uvw, (const Real *)wt,
+                         img_off, S_fix, W.slots, W.count, wpart, cnt);
+    else
+      hipLaunchKernelGGL((key_kernel<Real, TW>), key_grid, block, 0, s, G, B, nvis, uvw, (const Real *)wt, img_off,
+                         S_fix, W.slots, W.count, wpart, cnt);
+  };
   if (k->params.precision == WPROJ_F64) {
-    if (compact)
-      if (agg)
-        hipLaunchKernelGGL((key_agg_kernel<double, true>), agg_grid, agg_block, 0, s, G, B, nvis, uvw,
-                           (const double *)wt, img_off, S_fix, W.slots, W.count, wpart, cnt);
-      else
-        hipLaunchKernelGGL((key_kernel<double, true>), key_grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
-                           img_off, S_fix, W.slots, W.count, wpart, cnt);
+    if (tapword)
+      key_pass(double{}, std::true_type{});
     else
-      if (agg)
-        hipLaunchKernelGGL((key_agg_kernel<double, false>), agg_grid, agg_block, 0, s, G, B, nvis, uvw,
-                           (const double *)wt, img_off, S_fix, W.slots, W.count, wpart, cnt);
-      else
-        hipLaunchKernelGGL((key_kernel<double, false>), key_grid, block, 0, s, G, B, nvis, uvw, (const double *)wt,
-                           img_off, S_fix, W.slots, W.count, wpart, cnt);
+      key_pass(double{}, std::false_type{});
   } else {
-    if (compact)
-      if (agg)
-        hipLaunchKernelGGL((key_agg_kernel<float, true>), agg_grid, agg_block, 0, s, G, B, nvis, uvw,
-                           (const float *)wt, img_off, S_fix, W.slots, W.count, wpart, cnt);
-      else
-        hipLaunchKernelGGL((key_kernel<float, true>), key_grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
-                           img_off, S_fix, W.slots, W.count, wpart, cnt);
+    if (tapword)
+      key_pass(float{}, std::true_type{});
     else
-      if (agg)
-        hipLaunchKernelGGL((key_agg_kernel<float, false>), agg_grid, agg_block, 0, s, G, B, nvis, uvw,
-                           (const float *)wt, img_off, S_fix, W.slots, W.count, wpart, cnt);
-      else
-        hipLaunchKernelGGL((key_kernel<float, false>), key_grid, block, 0, s, G, B, nvis, uvw, (const float *)wt,
-                           img_off, S_fix, W.slots, W.count, wpart, cnt);
+      key_pass(float{}, std::false_type{});
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (wsum || counters) {
@@ -960,13 +927,13 @@ hipError_t launch_bin(const wproj_kernels *k, const BinShape &B, int64_t nvis, c
   }
   if ((e = launch_exclusive_scan(W.count, W.offset, B.n_keys, W.scan_tmp, s)) != hipSuccess) return e;
   if (k->params.precision == WPROJ_F64)
-    e = compact ? place_records<double, double2, RecordF64, true>(k, B, nvis, uvw, vis, wt, img_off, W, S_fix, s)
-                : place_records<double, double2, RecordF64, false>(k, B, nvis, uvw, vis, wt, img_off, W, S_fix, s);
-  else if (compact && vis)  // W V records of a fixed support: no tap word (12 bytes)
-    e = place_records<float, float2, RecordF32P, true>(k, B, nvis, uvw, vis, wt, img_off, W, S_fix, s);
+    e = tapword ? place_records<double, double2, RecordF64, true>(k, B, nvis, vis, wt, W, S_fix, s)
+                : place_records<double, double2, RecordF64, false>(k, B, nvis, vis, wt, W, S_fix, s);
+  else if (!tapword && vis)  // W V records of a fixed support: no tap word (12 bytes)
+    e = place_records<float, float2, RecordF32P, false>(k, B, nvis, vis, wt, W, S_fix, s);
   else
-    e = compact ? place_records<float, float2, RecordF32, true>(k, B, nvis, uvw, vis, wt, img_off, W, S_fix, s)
-                : place_records<float, float2, RecordF32, false>(k, B, nvis, uvw, vis, wt, img_off, W, S_fix, s);
+    e = tapword ? place_records<float, float2, RecordF32, true>(k, B, nvis, vis, wt, W, S_fix, s)
+                : place_records<float, float2, RecordF32, false>(k, B, nvis, vis, wt, W, S_fix, s);
   if (e != hipSuccess) return e;
   // work list: per tile, ceil(records / chunk) items
   hipLaunchKernelGGL(chunk_count_kernel, dim3(nblk(B.n_tiles, 256)), dim3(256), 0, s, W.offset,

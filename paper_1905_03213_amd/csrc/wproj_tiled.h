@@ -153,7 +153,7 @@ struct WorkItem {
 
 // Workspace carve-up for one call (all device pointers).
 struct BinWorkspace {
-  uint32_t *slots;     // [nvis]; [3 nvis] (slot, key, record word) when pack_sub
+  uint32_t *slots;     // [3 nvis] (slot, key, record word) when pack_sub, else [4 nvis] (and tap word)
   void *rec;           // [nvis] RecordF32 / RecordF32P / RecordF64
   uint32_t *count;     // [n_keys]
   uint32_t *offset;    // [n_keys + 1]
