@@ -39,8 +39,7 @@ constexpr uint32_t kFoldBit = 0x80000000u;
 // combine).  The scatter takes two per thread after the per-wavefront-run key pass with
 // packed records of a fixed support (cfg2 binning 1.20 ms against 1.24 with one and 1.28
 // with four), one otherwise (two measured slower: +0.06 ms after cfg4's aggregated key
-// pass, and +0.07 ms on cfg3's per-plane supports while the scatter still computed their
-// footprints again).
+// pass, +0.01 ms on cfg3's per-plane supports).
 constexpr int kBinBlock = 256;
 constexpr int kKeyVpt = 2;
 
