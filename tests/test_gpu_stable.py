@@ -99,11 +99,14 @@ def _plan_rows(params, uvw, wt, offs):
     return out
 
 
+@pytest.mark.parametrize("agg", [False, True])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("which", ["tracks", "variable_support", "multi_image", "fold", "crowded"])
-def test_stable_bins_keep_input_order(which, prec):
+def test_stable_bins_keep_input_order(which, prec, agg):
+    """Either key pass (per-wavefront runs, or counts aggregated per block) feeds the
+    stable sort the same keys."""
     params, uvw, vis, wt, offs = _case(which)
-    params = {**params, "precision": prec, "stable_bins": True}
+    params = {**params, "precision": prec, "stable_bins": True, "bin_aggregate": agg}
     key = _bin_keys(params, uvw, wt, offs)
     n_in = int((key != np.iinfo(np.int64).max).sum())
     want = np.argsort(key, kind="stable")[:n_in]
@@ -112,10 +115,11 @@ def test_stable_bins_keep_input_order(which, prec):
     assert (rows[n_in:] == 0xFFFFFFFF).all()
 
 
-@pytest.mark.parametrize("which", ["tracks", "multi_image", "crowded"])
-def test_atomic_bins_hold_the_oracle_rows(which):
+@pytest.mark.parametrize("agg", [False, True])
+@pytest.mark.parametrize("which", ["tracks", "variable_support", "multi_image", "crowded"])
+def test_atomic_bins_hold_the_oracle_rows(which, agg):
     params, uvw, vis, wt, offs = _case(which)
-    params = {**params, "precision": "f32"}
+    params = {**params, "precision": "f32", "bin_aggregate": agg}
     key = _bin_keys(params, uvw, wt, offs)
     n_in = int((key != np.iinfo(np.int64).max).sum())
     rows = _plan_rows(params, uvw, wt, offs)
