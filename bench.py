@@ -555,6 +555,8 @@ def main():
         torch.cuda.empty_cache()
         extra["cfg4"] = time_config("cfg4", dev, args, peak_lds)
         torch.cuda.empty_cache()
+        extra["cfg5"] = time_cfg5(dev, args)
+        torch.cuda.empty_cache()
         wl = synth.cfg2(device=dev, precision="f32", hours=args.hours)
 
     cpu = None
@@ -737,6 +739,69 @@ def measure_lds_peak():
     for mode, name in ((0, "read"), (1, "write"), (2, "read_add_write")):
         rates[name] = max(W.measure_lds(mode, rounds=4096)[0] for _ in range(3))
     return rates
+
+
+def time_cfg5(dev, args):
+    """The differentiable forward model: chi^2 of a 2048^2 FP32 model image against 1.01e7
+    visibilities and its gradient, through the autograd function (forward: correction,
+    forward FFT, binning, degridding; backward: binning and gridding of W r, inverse FFT,
+    correction).  One step is one loss and one gradient; timed with the rows binned in
+    every call and with them binned once (a plan, as an imaging loop on fixed rows would)."""
+    import torch
+
+    import paper_1905_03213_amd as W
+    import synth
+    from paper_1905_03213_amd.autograd import chi2, make_plan, predict
+
+    t0 = time.time()
+    wl = synth.cfg5(device=dev)
+    n = wl.params["n"]
+    k = W.make_kernels({**wl.params, "precision": "f32", "algorithm": "tiled"})
+    vis = wl.vis.to(torch.complex64)
+    wt = torch.ones(wl.nvis, dtype=torch.float32, device=dev)
+    tile, chunk = W.autotune(k, wl.uvw, vis, wt)
+    model = torch.as_tensor(synth.cfg5_model_image(n), dtype=torch.float32, device=dev)[None]
+    with torch.no_grad():
+        vis_obs = predict(model, k, wl.uvw) + vis  # model prediction plus the workload's noise
+    image = (0.9 * model).requires_grad_()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    steps = max(3, args.steps // 2)
+
+    def timed(plan):
+        def step():
+            image.grad = None
+            loss = chi2(image, k, wl.uvw, vis_obs, wt, plan=plan)
+            loss.backward()
+
+        for _ in range(max(1, args.warmup)):
+            step()
+        torch.cuda.synchronize()
+        k.profile(True)
+        k.profile_read()
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        ph = k.profile_read()
+        k.profile(False)
+        # per step: the phase's total time over the steps
+        return ms, {p: v / steps for p, (v, c) in ph.items() if c}
+
+    ms, per = timed(None)
+    plan = make_plan(k, wl.uvw)
+    ms_p, per_p = timed(plan)
+    plan.free()
+    out = {"workload": f"cfg5: {n}^2 FP32 model image, {wl.nvis} visibilities, chi^2 and its gradient",
+           "ms_per_step": ms, "mvis_per_s": wl.nvis / ms / 1e3, "phases_ms_per_step": per,
+           "planned": {"ms_per_step": ms_p, "mvis_per_s": wl.nvis / ms_p / 1e3, "phases_ms_per_step": per_p},
+           "tuning": {"tile": tile, "chunk": chunk}, "generated_s": time.time() - t0}
+    log(f"cfg5: {ms:.3f} ms/step (loss + gradient), {wl.nvis / ms / 1e3:.1f} Mvis/s, phases {per}; "
+        f"rows binned once: {ms_p:.3f} ms/step, {wl.nvis / ms_p / 1e3:.1f} Mvis/s, phases {per_p}")
+    k.free()
+    return out
 
 
 def time_config(name, dev, args, peak_lds):

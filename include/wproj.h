@@ -375,6 +375,25 @@ int wproj_degrid_planned(const wproj_plan *plan, const void *model_grid, void *v
 int wproj_plan_rows(const wproj_plan *plan, uint32_t *rows, void *stream);
 
 /*
+ * The loss of the differentiable forward model (model image -> predicted visibilities by
+ * wproj_image(IMAGE_TO_GRID) then wproj_degrid) and its gradient, in one pass.  The paper
+ * defines no loss (its imager grids and images); this is the weighted least-squares
+ * misfit of the visibilities:
+ *   chi2[0] = sum_j w_j |o_j - p_j|^2                (FP64; overwritten, not accumulated)
+ *   grad_j  = -2 w_j (o_j - p_j)                    (= d chi2/d Re p_j + i d chi2/d Im p_j)
+ * precision: wproj_precision of the arrays (WPROJ_F64: complex double and double weights;
+ * otherwise complex float and float weights).  vis_obs o, pred p: [nvis] complex,
+ * device; weight w: [nvis] real, device, nullable (all 1); chi2: one double, device;
+ * grad: [nvis] complex, device, nullable (not written).  The sum runs in a fixed order,
+ * so chi2 is reproducible bit for bit.  workspace: device, at least
+ * wproj_chi2_workspace_size() bytes (per-block partial sums); calls that share a
+ * workspace must not overlap.  Errors: WPROJ_EINVAL, WPROJ_EWORKSPACE, WPROJ_EHIP.
+ */
+int64_t wproj_chi2_workspace_size(void);
+int wproj_chi2(int precision, int64_t nvis, const void *vis_obs, const void *pred, const void *weight,
+               double *chi2, void *grad, void *workspace, int64_t workspace_bytes, void *stream);
+
+/*
  * Per-visibility footprint: the uvw -> grid step every gridding and degridding call
  * takes, exported.  For visibility j, out[6 j .. 6 j + 5] (int32, device) =
  * {x0, y0, ou, ov, p, class}: first footprint cell (x0, y0), sub-kernel (ou, ov), w-plane

@@ -18,6 +18,7 @@ from .wproj import (  # noqa: F401
     WprojError,
     autotune,
     check_weights,
+    chi2,
     degrid,
     footprints,
     gather_rows,

@@ -24,7 +24,8 @@ EXPORTED = ("wproj_make_kernels", "wproj_free_kernels", "wproj_export", "wproj_w
             "wproj_profile", "wproj_profile_read", "wproj_last_error", "wproj_version",
             "wproj_footprints", "wproj_regroup_workspace_size", "wproj_regroup_rows",
             "wproj_gather_rows", "wproj_plan_create", "wproj_plan_free", "wproj_grid_planned",
-            "wproj_degrid_planned", "wproj_plan_rows", "wproj_grid_noalloc", "wproj_noalloc_scratch_bytes",
+            "wproj_degrid_planned", "wproj_plan_rows", "wproj_chi2", "wproj_chi2_workspace_size",
+            "wproj_grid_noalloc", "wproj_noalloc_scratch_bytes",
             "wproj_check_weights", "wproj_measure_lds", "wproj_measure_vmem", "wproj_regroup_channels")
 PHASES = ("bin", "grid", "plain", "fft", "correct", "degrid", "reduce")
 
@@ -94,6 +95,9 @@ def lib():
     L.wproj_grid_planned.argtypes = [vp, vp, vp, vp]
     L.wproj_degrid_planned.argtypes = [vp, vp, vp, vp]
     L.wproj_plan_rows.argtypes = [vp, vp, vp]
+    L.wproj_chi2.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, i64, vp]
+    L.wproj_chi2_workspace_size.argtypes = []
+    L.wproj_chi2_workspace_size.restype = i64
     L.wproj_regroup_workspace_size.argtypes = [i64, ctypes.c_int32]
     L.wproj_regroup_workspace_size.restype = i64
     L.wproj_regroup_rows.argtypes = [i64, vp, vp, ctypes.c_int32, vp, vp, vp, vp, i64, vp]
@@ -109,7 +113,8 @@ def lib():
                  "wproj_degrid", "wproj_image", "wproj_autotune", "wproj_tuning", "wproj_profile",
                  "wproj_profile_read", "wproj_version", "wproj_footprints", "wproj_regroup_rows",
                  "wproj_gather_rows", "wproj_plan_create", "wproj_plan_free", "wproj_grid_planned",
-                 "wproj_degrid_planned", "wproj_plan_rows", "wproj_grid_noalloc", "wproj_check_weights",
+                 "wproj_degrid_planned", "wproj_plan_rows", "wproj_chi2", "wproj_grid_noalloc",
+                 "wproj_check_weights",
                  "wproj_measure_lds",
                  "wproj_measure_vmem", "wproj_regroup_channels"):
         getattr(L, name).restype = i32

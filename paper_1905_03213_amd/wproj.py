@@ -181,6 +181,29 @@ def grid(k: Kernels, uvw: torch.Tensor, vis: torch.Tensor, weight: torch.Tensor,
         _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
 
 
+def chi2(vis_obs: torch.Tensor, pred: torch.Tensor, weight: Optional[torch.Tensor] = None,
+         grad: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+         stream=None) -> torch.Tensor:
+    """wproj_chi2: sum_j w_j |o_j - p_j|^2 as a one-element float64 device tensor; if grad
+    is given, -2 w_j (o_j - p_j) is written into it.  complex128 arrays run in FP64,
+    complex64 in FP32 (weights of the matching real type)."""
+    if pred.dtype not in (torch.complex64, torch.complex128):
+        raise TypeError("pred must be complex64 or complex128")
+    f64 = pred.dtype == torch.complex128
+    real = torch.float64 if f64 else torch.float32
+    nvis = int(pred.numel())
+    out = torch.empty(1, dtype=torch.float64, device=pred.device)
+    if workspace is None:
+        workspace = torch.empty(int(_lib.lib().wproj_chi2_workspace_size()), dtype=torch.uint8,
+                                device=pred.device)
+    _lib.check("wproj_chi2", _lib.lib().wproj_chi2(
+        _lib.F64 if f64 else _lib.F32, nvis, _ptr(vis_obs, "vis_obs", pred.dtype, nvis),
+        _ptr(pred, "pred", pred.dtype, nvis), _ptr(weight, "weight", real, nvis),
+        _ptr(out, "chi2", torch.float64, 1), _ptr(grad, "grad", pred.dtype, nvis),
+        _ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
+    return out
+
+
 def check_weights(k: Kernels, weight_sum: torch.Tensor, stream=None):
     """wproj_check_weights: waits for the stream; raises WprojError (code WPROJ_EEMPTY = -7)
     when an image's sum of weights is 0 (that image comes out of GRID_TO_IMAGE as zeros)."""

@@ -121,3 +121,15 @@ def test_rate_measurements_check_arguments():
     assert L.wproj_measure_vmem(8, 16, None, None, None) == -1
     assert L.wproj_measure_vmem(2, 16, ctypes.byref(bps), None, None) == -1
     assert b"width" in L.wproj_last_error()
+
+
+def test_chi2_argument_checks():
+    L = _lib.lib()
+    assert L.wproj_chi2_workspace_size() > 0
+    d = ctypes.c_double()
+    # unknown precision, negative count, no output, no inputs, no workspace
+    assert L.wproj_chi2(7, 0, None, None, None, ctypes.byref(d), None, ctypes.byref(d), 1 << 20, None) == -1
+    assert L.wproj_chi2(1, -1, None, None, None, ctypes.byref(d), None, ctypes.byref(d), 1 << 20, None) == -1
+    assert L.wproj_chi2(1, 0, None, None, None, None, None, ctypes.byref(d), 1 << 20, None) == -1
+    assert L.wproj_chi2(1, 5, None, None, None, ctypes.byref(d), None, ctypes.byref(d), 1 << 20, None) == -1
+    assert L.wproj_chi2(1, 0, None, None, None, ctypes.byref(d), None, None, 0, None) == -5

@@ -105,3 +105,76 @@ def test_chi2_finite_differences_fp64():
             fd = (chi2(I + e, k, U, Vo, Wt) - chi2(I - e, k, U, Vo, Wt)).item() / (2 * h)
         assert abs(fd - g[y, x]) <= 1e-6 * max(1.0, np.abs(g).max())
     k.free()
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-11), ("f32", 2e-5)])
+def test_planned_model_matches_oracle_and_unplanned(prec, tol):
+    """predict and chi2 through a plan (the rows binned once, then degridded forward and
+    gridded backward through it) against the oracle, and against the same model binning
+    the rows in every call."""
+    from paper_1905_03213_amd.autograd import make_plan
+
+    params, plan, tabs, uvw, v_obs, wt, rng = _problem(prec)
+    n = plan.n
+    cd = torch.complex128 if prec == "f64" else torch.complex64
+    rd = torch.float64 if prec == "f64" else torch.float32
+    img0 = np.zeros((n, n))
+    q = n // 4
+    img0[q:n - q, q:n - q] = 0.01 * rng.standard_normal((n - 2 * q, n - 2 * q))
+    img0 = img0.astype(np.float32 if prec != "f64" else np.float64)
+    k = W.make_kernels(params)
+    U = torch.as_tensor(uvw).cuda()
+    Vo = torch.as_tensor(v_obs).to(cd).cuda()
+    Wt = torch.as_tensor(wt).to(rd).cuda()
+    P = make_plan(k, U)
+    grads, preds = [], []
+    for p in (P, None):
+        I = torch.tensor(img0, device="cuda", requires_grad=True)
+        preds.append(predict(I, k, U, plan=p).detach().to(torch.complex128).cpu().numpy())
+        chi2(I, k, U, Vo, Wt, plan=p).backward()
+        grads.append(I.grad.double().cpu().numpy())
+    ref_pred = R.predict(plan, tabs, uvw, img0.astype(np.float64))
+    assert rel_max(preds[0], ref_pred) <= tol
+    ref_grad = R.chi2_grad(plan, tabs, uvw, Vo.to(torch.complex128).cpu().numpy(),
+                           Wt.double().cpu().numpy(), img0.astype(np.float64))[0]
+    inner = (slice(n // 4, n - n // 4), slice(n // 4, n - n // 4))
+    r_ref = Vo.to(torch.complex128).cpu().numpy() - ref_pred
+    bound = grad_bound(float(np.sqrt(np.mean(np.abs(preds[0] - ref_pred) ** 2))),
+                       float(np.sqrt(np.mean(np.abs(r_ref) ** 2))), tol)
+    assert rel_max(grads[0][inner], ref_grad[inner]) <= bound
+    # the planned and per-call models agree to the rounding of their accumulation order
+    assert rel_max(preds[0], preds[1]) <= (1e-12 if prec == "f64" else 1e-6)
+    assert rel_max(grads[0][inner], grads[1][inner]) <= (1e-9 if prec == "f64" else bound)
+    P.free()
+    k.free()
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("n", [0, 1, 255, 257, 300001])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_chi2_kernel_matches_numpy(prec, n, weighted):
+    """wproj_chi2 against the definition in numpy: the residual in the arrays' precision,
+    its weighted square summed in FP64; the gradient -2 w r; the same sum bit for bit on
+    a second call (fixed reduction order)."""
+    rng = np.random.default_rng(n + 7)
+    cd, rd = (np.complex128, np.float64) if prec == "f64" else (np.complex64, np.float32)
+    o = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(cd)
+    p = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(cd)
+    w = rng.uniform(0.5, 2.0, n).astype(rd) if weighted else np.ones(n, dtype=rd)
+    O, P = torch.as_tensor(o).cuda(), torch.as_tensor(p).cuda()
+    Wt = torch.as_tensor(w).cuda() if weighted else None
+    G = torch.empty_like(P)
+    loss = W.chi2(O, P, Wt, grad=G)
+    again = W.chi2(O, P, Wt)
+    torch.cuda.synchronize()
+    rr = (o.real - p.real).astype(rd)
+    ri = (o.imag - p.imag).astype(rd)
+    ref = float(np.sum(w.astype(np.float64) * (rr.astype(np.float64) ** 2 + ri.astype(np.float64) ** 2)))
+    got = float(loss.item())
+    assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref))
+    assert got == float(again.item())
+    if n:
+        g = G.cpu().numpy()
+        two = rd(-2)
+        assert np.allclose(g.real, (two * w) * rr, rtol=1e-6 if prec == "f32" else 1e-15, atol=0)
+        assert np.allclose(g.imag, (two * w) * ri, rtol=1e-6 if prec == "f32" else 1e-15, atol=0)
