@@ -448,8 +448,8 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
   }
 }
 
-// Adds the partial tiles to the grid.  One thread per grid cell sums, in FP64, every
-// work item's partial value for that cell: the items of the cell's own tile and those of
+// Adds the partial tiles to the grid.  One thread per grid cell (each thread takes two
+// cells of a column) sums, in FP64, every work item's partial value for that cell: the items of the cell's own tile and those of
 // the tiles to its left/above whose halo reaches it (items of tile t are contiguous in
 // the work list: [choff[t], choff[t + 1])).  Each cell has exactly one writer, so the
 // grid update needs no atomics and the result does not depend on scheduling.
@@ -457,31 +457,48 @@ template <typename Real>
 __global__ void __launch_bounds__(256)
     tile_reduce_kernel(Geometry G, BinShape B, int rows, const typename Cx<Real>::T *__restrict__ partial,
                        const uint32_t *__restrict__ choff, Real *grid) {
-  // blockIdx.x * 256 + threadIdx.x is the column, blockIdx.y the row, blockIdx.z steps
-  // through the grids
-  const int X = (int)(blockIdx.x * 256 + threadIdx.x), Y = (int)blockIdx.y;
+  using C2 = typename Cx<Real>::T;
+  // blockIdx.x * 256 + threadIdx.x is the column; a thread takes rows 2 blockIdx.y and
+  // 2 blockIdx.y + 1 (one tile row, since tiles have an even side), whose work items and
+  // their offsets it looks up once; blockIdx.z steps through the grids
+  const int X = (int)(blockIdx.x * 256 + threadIdx.x), Y = 2 * (int)blockIdx.y;
   if (X >= G.n) return;
   const int64_t cells = (int64_t)G.n * G.n;
   const int T = B.tile;
   const int tx = X >> B.log2_tile, ty = Y >> B.log2_tile, lx = X & (T - 1), ly = Y & (T - 1);
   for (int img = (int)blockIdx.z; img < G.n_grids; img += (int)gridDim.z) {
-    double sr = 0.0, si = 0.0;
+    double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
     for (int dy = 0; dy <= ty && ly + dy * T < rows; ++dy) {
+      const bool second = ly + 1 + dy * T < rows;  // row Y + 1 is inside this tile's copy too
       for (int dx = 0; dx <= tx && lx + dx * T < rows; ++dx) {
         const int64_t tile = ((int64_t)img * B.nty + (ty - dy)) * B.ntx + (tx - dx);
         const int off = (ly + dy * T) * rows + (lx + dx * T);
         const uint32_t i1 = choff[tile + 1];
         for (uint32_t i = choff[tile]; i < i1; ++i) {
-          const auto v = partial[(size_t)i * rows * rows + off];
-          sr += (double)v.x;
-          si += (double)v.y;
+          const C2 *p = partial + (size_t)i * rows * rows + off;
+          const C2 v0 = p[0];
+          sr0 += (double)v0.x;
+          si0 += (double)v0.y;
+          if (second) {
+            const C2 v1 = p[rows];
+            sr1 += (double)v1.x;
+            si1 += (double)v1.y;
+          }
         }
       }
     }
-    if (sr != 0.0 || si != 0.0) {
-      Real *g = grid + 2 * (cells * img + (int64_t)Y * G.n + X);
-      g[0] = (Real)((double)g[0] + sr);
-      g[1] = (Real)((double)g[1] + si);
+    C2 *g = reinterpret_cast<C2 *>(grid) + (cells * img + (int64_t)Y * G.n + X);
+    if (sr0 != 0.0 || si0 != 0.0) {
+      C2 v = g[0];
+      v.x = (Real)((double)v.x + sr0);
+      v.y = (Real)((double)v.y + si0);
+      g[0] = v;
+    }
+    if (sr1 != 0.0 || si1 != 0.0) {
+      C2 v = g[G.n];
+      v.x = (Real)((double)v.x + sr1);
+      v.y = (Real)((double)v.y + si1);
+      g[G.n] = v;
     }
   }
 }
@@ -518,7 +535,7 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
 template <typename Real>
 hipError_t launch_reduce(const wproj_kernels *k, const BinShape &B, const TileShape &ts,
                          const BinWorkspace &W, void *grid, hipStream_t s) {
-  const dim3 grid3((unsigned)((k->params.n + 255) / 256), (unsigned)k->params.n,
+  const dim3 grid3((unsigned)((k->params.n + 255) / 256), (unsigned)(k->params.n / 2),
                    (unsigned)std::min<int64_t>(k->geo.n_grids, 65535));
   hipLaunchKernelGGL(tile_reduce_kernel<Real>, grid3, dim3(256), 0,
                      s, k->geo, B, ts.rows, (const typename Cx<Real>::T *)W.partial, W.choff,
