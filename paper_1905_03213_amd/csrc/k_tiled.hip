@@ -64,6 +64,9 @@ template <> struct Cx<double> { using T = double2; };
 // loads are all issued before the first is consumed, so up to kGroup memory latencies
 // overlap per wave.
 constexpr int kGroup = 8;
+// The same for the per-record-support path, whose table misses reach past L2 (cfg3's
+// 4096^2 rows: 4.03 ms with 8, 3.94 with 16, 4.72 with 32).
+constexpr int kVarGroup = 16;
 
 // One tap of an FP32 or FP16 table loaded through a buffer resource (lane's byte offset
 // in the vector offset, the sub-kernel's in the scalar offset), kept raw until use.
@@ -347,7 +350,7 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
     } else if constexpr (kHasTap<Rec> && std::is_same_v<Real, float>) {
       // Per-record supports with FP32 arithmetic.  Records arrive 64 at a time (one
       // coalesced load, readlane broadcasts).  A record with S <= 8 takes one pass, lane t
-      // tap t; its taps load one group of kGroup records ahead, at a wave-uniform scalar
+      // tap t; its taps load one group of kVarGroup records ahead, at a wave-uniform scalar
       // offset (the table carries 64 zero taps past its end, so lanes t >= S^2 of its last
       // sub-kernel stay inside it).  The lane's cell offset follows the support and is
       // recomputed only when the support changes (a tile's records come plane by plane).
@@ -364,18 +367,18 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         s_cur = Sn;
       };
       const uint32_t vlane = (uint32_t)lane * (uint32_t)sizeof(Tab);
-      auto fetch_group = [&](const Rec &batch, int g, Raw (&dst)[kGroup]) {
+      auto fetch_group = [&](const Rec &batch, int g, Raw (&dst)[kVarGroup]) {
 #pragma unroll
-        for (int i = 0; i < kGroup; ++i) {
-          const uint32_t tp = bcast(batch.tap, g * kGroup + i);
+        for (int i = 0; i < kVarGroup; ++i) {
+          const uint32_t tp = bcast(batch.tap, g * kVarGroup + i);
           if ((tp >> kTapBits) < 8u) dst[i] = TapRaw<Tab>::load(tab_rsrc, vlane, (tp & kTapMask) * (uint32_t)sizeof(Tab));
         }
       };
-      auto accumulate_group = [&](const Rec &batch, int g, const Raw (&src)[kGroup]) {
+      auto accumulate_group = [&](const Rec &batch, int g, const Raw (&src)[kVarGroup]) {
         bool large = false;
 #pragma unroll
-        for (int i = 0; i < kGroup; ++i) {
-          const int j = g * kGroup + i;
+        for (int i = 0; i < kVarGroup; ++i) {
+          const int j = g * kVarGroup + i;
           const uint32_t tp = bcast(batch.tap, j);
           const int Sr = (int)(tp >> kTapBits) + 1;
           if (Sr <= 8) {
@@ -390,8 +393,8 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         // records with S > 8 (several passes), their taps loaded as they go
         if (large) {
 #pragma unroll 1
-          for (int i = 0; i < kGroup; ++i) {
-            const int j = g * kGroup + i;
+          for (int i = 0; i < kVarGroup; ++i) {
+            const int j = g * kVarGroup + i;
             const uint32_t tp = bcast(batch.tap, j);
             const int Sr = (int)(tp >> kTapBits) + 1;
             if (Sr <= 8) continue;
@@ -411,12 +414,12 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
         Rec nxt;
         const bool more = b + 64 < n_rec;
         if (more) load_batch(b + 64, nxt);
-        Raw c0[kGroup], c1[kGroup];
+        Raw c0[kVarGroup], c1[kVarGroup];
         fetch_group(cur, 0, c0);
-        for (int g = 0; g < 64 / kGroup; g += 2) {
+        for (int g = 0; g < 64 / kVarGroup; g += 2) {
           fetch_group(cur, g + 1, c1);
           accumulate_group(cur, g, c0);
-          if (g + 2 < 64 / kGroup) fetch_group(cur, g + 2, c0);
+          if (g + 2 < 64 / kVarGroup) fetch_group(cur, g + 2, c0);
           accumulate_group(cur, g + 1, c1);
         }
         if (more) cur = nxt;
