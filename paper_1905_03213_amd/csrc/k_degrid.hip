@@ -82,7 +82,7 @@ __device__ inline double group8_sum(double v) {
 
 template <typename Real, typename Rec, typename Tab, int S>
 __global__ void __launch_bounds__(64 * kDegridWaves)
-    tiled_degrid_kernel(Geometry G, BinShape B, int pitch, int rows, int wave_lds,
+    tiled_degrid_kernel(Geometry G, BinShape B, int pitch, int rows,
                         const Tab *__restrict__ tab, const Rec *__restrict__ rec,
                         const WorkItem *__restrict__ items, const uint32_t *__restrict__ order,
                         const uint32_t *__restrict__ n_items_ptr,
@@ -272,7 +272,7 @@ __device__ inline void tap_pair(const TapPair<float2>::Raw &v, float2 &a, float2
 
 template <typename Tab, int S>
 __global__ void __launch_bounds__(64 * kTeamWaves)
-    tap_lane_degrid_kernel(Geometry G, BinShape B, int pitch, int rows, int wave_lds,
+    tap_lane_degrid_kernel(Geometry G, BinShape B, int pitch, int rows,
                            const Tab *__restrict__ tab, uint32_t tab_bytes,
                            const RecordF32 *__restrict__ rec, const WorkItem *__restrict__ items,
                            const uint32_t *__restrict__ order, const uint32_t *__restrict__ n_items_ptr,
@@ -450,9 +450,8 @@ hipError_t launch_tap_lane(const wproj_kernels *k, const BinShape &B, const Tile
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   if (!k->d_tab_pair || k->pair_stride != pair_table_stride(S)) return hipErrorInvalidValue;
   const int64_t n_sub = (int64_t)k->params.n_wplanes * k->params.oversample * k->params.oversample;
-  const int wave_lds = (int)(ts.lds_bytes / sizeof(float2));
   hipLaunchKernelGGL(kern, dim3((unsigned)(k->n_cu * per_cu)), dim3(64 * wpb), lds, s, k->geo, B,
-                     ts.pitch, ts.rows, wave_lds, (const Tab *)k->d_tab_pair,
+                     ts.pitch, ts.rows, (const Tab *)k->d_tab_pair,
                      (uint32_t)(n_sub * k->pair_stride * (int64_t)sizeof(Tab)), (const RecordF32 *)W.rec,
                      W.items, W.order, W.choff + B.n_tiles, W.counter, (const float2 *)model, (float2 *)out);
   return hipGetLastError();
@@ -472,9 +471,8 @@ hipError_t launch_one(const wproj_kernels *k, const BinShape &B, const TileShape
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb, lds);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
-  const int wave_lds = (int)(ts.lds_bytes / sizeof(C2));
   hipLaunchKernelGGL(kern, dim3((unsigned)(k->n_cu * per_cu)), dim3(64 * wpb), lds, s, k->geo, B,
-                     ts.pitch, ts.rows, wave_lds, (const Tab *)k->d_tab, (const Rec *)W.rec,
+                     ts.pitch, ts.rows, (const Tab *)k->d_tab, (const Rec *)W.rec,
                      W.items, W.order, W.choff + B.n_tiles, W.counter, (const C2 *)model, (C2 *)out);
   return hipGetLastError();
 }
