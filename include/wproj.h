@@ -262,8 +262,10 @@ typedef enum {
  *   IDFT(G)[y][x] = sum_{Y,X} G[Y][X] exp(+2 pi i ((X - n/2)(x - n/2) + (Y - n/2)(y - n/2))/n)
  *   DFT(I)[Y][X]  = sum_{y,x} I[y][x] exp(-2 pi i ((X - n/2)(x - n/2) + (Y - n/2)(y - n/2))/n)
  * (the paper's final IFFT, Sections 2.1-2.2; rocFFT does the 2D transforms).
- * GRID_TO_IMAGE*: grid is transformed IN PLACE (its contents are destroyed) and
- * image is written.  IMAGE_TO_GRID: image is read and grid is overwritten.
+ * GRID_TO_IMAGE*: grid's contents are destroyed (without w-stacking the image's real
+ * transform takes the grid's Hermitian half spectrum, formed in the workspace, and
+ * writes its output over the grid; with w-stacking each layer is transformed in place)
+ * and image is written.  IMAGE_TO_GRID: image is read and grid is overwritten.
  * weight_sum (float64 [n_images], device) is read only by GRID_TO_IMAGE; an image
  * whose sum is 0 is written as zeros (see wproj_check_weights).
  * Errors: WPROJ_EINVAL, WPROJ_EWORKSPACE, WPROJ_EFFT.

@@ -175,6 +175,7 @@ void destroy(wproj_kernels *k) {
   for (hipEvent_t e : k->event_pool) (void)hipEventDestroy(e);
   if (k->fft_fwd) rocfft_plan_destroy(k->fft_fwd);
   if (k->fft_inv) rocfft_plan_destroy(k->fft_inv);
+  if (k->fft_c2r) rocfft_plan_destroy(k->fft_c2r);
   (void)hipFree(k->d_supp);
   (void)hipFree(k->d_tab_off);
   (void)hipFree(k->d_tab);
@@ -535,6 +536,18 @@ int wproj_make_kernels(const wproj_params *params, void *stream, wproj_kernels *
   rocfft_plan_get_work_buffer_size(k->fft_inv, &w1);
   rocfft_plan_get_work_buffer_size(k->fft_fwd, &w2);
   k->fft_work_bytes = std::max(w1, w2);
+  // grid -> image without w-stacking: the image is Re IFFT(G) = IFFT of G's Hermitian part,
+  // a complex-to-real transform of the half spectrum (half the work of the complex one).
+  // Out of place: the half spectrum in the workspace, the real output over the grid.
+  if (params->w_mode != WPROJ_W_STACK) {
+    if (rocfft_plan_create(&k->fft_c2r, rocfft_placement_notinplace, rocfft_transform_type_real_inverse, fp, 2,
+                           lengths, (size_t)G.n_grids, nullptr) != rocfft_status_success)
+      return fail(WPROJ_EFFT, "rocfft_plan_create (complex to real) failed for %dx%d x %d", n, n, G.n_grids);
+    const size_t real = params->precision == WPROJ_F64 ? 8 : 4;
+    k->herm_bytes = (size_t)G.n_grids * (size_t)n * (size_t)(n / 2 + 1) * 2 * real;
+    rocfft_plan_get_work_buffer_size(k->fft_c2r, &k->c2r_work_bytes);
+    k->fft_work_bytes = std::max(k->fft_work_bytes, (size_t)align_up((int64_t)k->herm_bytes) + k->c2r_work_bytes);
+  }
 
   HIP_TRY(hipStreamSynchronize(s));
   guard.k = nullptr;
@@ -824,13 +837,32 @@ int wproj_image(const wproj_kernels *k, int direction, void *grid, void *image,
       return fail(WPROJ_EFFT, "rocfft_execute (forward) failed");
     return WPROJ_OK;
   }
+  const double *wsum = direction == WPROJ_GRID_TO_IMAGE ? weight_sum : nullptr;
+  if (k->fft_c2r) {
+    // twice the Hermitian half spectrum into the workspace, its complex-to-real inverse
+    // over the grid, then the correction (with the factor 1/2)
+    char *half = (char *)workspace;
+    {
+      PhaseTimer pt(k, WPROJ_PHASE_FFT, s);
+      HIP_TRY(launch_hermitian_half(k, grid, half, s));
+      if (k->c2r_work_bytes > 0)
+        rocfft_execution_info_set_work_buffer(info, half + align_up((int64_t)k->herm_bytes), k->c2r_work_bytes);
+      void *in[1] = {half};
+      void *outp[1] = {grid};
+      if (rocfft_execute(k->fft_c2r, in, outp, info) != rocfft_status_success)
+        return fail(WPROJ_EFFT, "rocfft_execute (complex to real) failed");
+    }
+    PhaseTimer pt(k, WPROJ_PHASE_CORRECT, s);
+    HIP_TRY(launch_g2i_correct_real(k, grid, image, wsum, s));
+    return WPROJ_OK;
+  }
   {
     PhaseTimer pt(k, WPROJ_PHASE_FFT, s);
     if (rocfft_execute(k->fft_inv, buf, nullptr, info) != rocfft_status_success)
       return fail(WPROJ_EFFT, "rocfft_execute (inverse) failed");
   }
   PhaseTimer pt(k, WPROJ_PHASE_CORRECT, s);
-  HIP_TRY(launch_g2i_correct(k, grid, image, direction == WPROJ_GRID_TO_IMAGE ? weight_sum : nullptr, s));
+  HIP_TRY(launch_g2i_correct(k, grid, image, wsum, s));
   return WPROJ_OK;
 }
 

@@ -46,6 +46,51 @@ __global__ void __launch_bounds__(kPixThreads)
   }
 }
 
+// Twice the Hermitian part of each grid on the half spectrum the complex-to-real
+// transform reads: H[ky][kx] = G[ky][kx] + conj(G[-ky][-kx]) (indices mod n), kx in
+// [0, n/2].  The inverse transform of the Hermitian part is the real part of the inverse
+// transform of G.
+template <typename Real>
+__global__ void __launch_bounds__(kPixThreads)
+    hermitian_half_kernel(int n, int n_grids, const Real *__restrict__ G, Real *__restrict__ H) {
+  const int kx = (int)(blockIdx.x * kPixThreads + threadIdx.x), ky = (int)blockIdx.y;
+  const int hw = n / 2 + 1;
+  if (kx >= hw) return;
+  const int64_t cells = (int64_t)n * n, half = (int64_t)n * hw;
+  const int my = ky == 0 ? 0 : n - ky, mx = kx == 0 ? 0 : n - kx;
+  for (int i = (int)blockIdx.z; i < n_grids; i += (int)gridDim.z) {
+    const Real *g = G + 2 * cells * i;
+    const int64_t a = 2 * ((int64_t)ky * n + kx), b = 2 * ((int64_t)my * n + mx);
+    Real *h = H + 2 * (half * i + (int64_t)ky * hw + kx);
+    h[0] = g[a] + g[b];
+    h[1] = g[a + 1] - g[b + 1];
+  }
+}
+
+// g2i_kernel on the real output R = 2 Re IFFT(G) of the complex-to-real transform.
+template <typename Real>
+__global__ void __launch_bounds__(kPixThreads)
+    g2i_real_kernel(int n, int n_images, const Real *__restrict__ R, const double *__restrict__ kappa,
+                    const double *__restrict__ wsum, Real *__restrict__ img) {
+  const int x = (int)(blockIdx.x * kPixThreads + threadIdx.x), y = (int)blockIdx.y;
+  if (x >= n) return;
+  const int64_t cells = (int64_t)n * n;
+  const int h = n / 2;
+  const int ys = y + h < n ? y + h : y - h;
+  const int xs = x + h < n ? x + h : x - h;
+  const double kk = 0.5 * kappa[x] * kappa[y];
+  for (int i = (int)blockIdx.z; i < n_images; i += (int)gridDim.z) {
+    const double re = (double)R[cells * i + (int64_t)ys * n + xs];
+    double scale = kk;
+    if (wsum != nullptr) {
+      const double s = wsum[i];
+      scale = s != 0.0 ? scale / s : 0.0;
+    }
+    const double v = ((x + y) & 1) ? -re : re;
+    img[cells * i + (int64_t)y * n + x] = (Real)(v * scale);
+  }
+}
+
 template <typename Real>
 __global__ void __launch_bounds__(kPixThreads)
     i2g_kernel(int n, int n_images, const Real *__restrict__ img, const double *__restrict__ kappa,
@@ -180,6 +225,32 @@ hipError_t launch_g2i_correct(const wproj_kernels *k, const void *fgrid, void *i
                        wsum, (double *)image);
   else
     hipLaunchKernelGGL(g2i_kernel<float>, grid, block, 0, s, n, ni, (const float *)fgrid, k->d_kappa,
+                       wsum, (float *)image);
+  return hipGetLastError();
+}
+
+hipError_t launch_hermitian_half(const wproj_kernels *k, const void *grid, void *half, hipStream_t s) {
+  const int n = k->params.n, ng = k->geo.n_grids;
+  const dim3 g3((unsigned)((n / 2 + 1 + kPixThreads - 1) / kPixThreads), (unsigned)n,
+                std::min((unsigned)ng, kMaxGridZ));
+  if (k->params.precision == WPROJ_F64)
+    hipLaunchKernelGGL(hermitian_half_kernel<double>, g3, dim3(kPixThreads), 0, s, n, ng, (const double *)grid,
+                       (double *)half);
+  else
+    hipLaunchKernelGGL(hermitian_half_kernel<float>, g3, dim3(kPixThreads), 0, s, n, ng, (const float *)grid,
+                       (float *)half);
+  return hipGetLastError();
+}
+
+hipError_t launch_g2i_correct_real(const wproj_kernels *k, const void *real, void *image,
+                                   const double *wsum, hipStream_t s) {
+  const int n = k->params.n, ni = k->params.n_images;
+  const dim3 grid = pixel_grid(n, ni), block(kPixThreads);
+  if (k->params.precision == WPROJ_F64)
+    hipLaunchKernelGGL(g2i_real_kernel<double>, grid, block, 0, s, n, ni, (const double *)real, k->d_kappa,
+                       wsum, (double *)image);
+  else
+    hipLaunchKernelGGL(g2i_real_kernel<float>, grid, block, 0, s, n, ni, (const float *)real, k->d_kappa,
                        wsum, (float *)image);
   return hipGetLastError();
 }

@@ -191,6 +191,10 @@ struct wproj_kernels {
   double *d_kappa = nullptr;
   double *d_taper = nullptr;
   rocfft_plan fft_fwd = nullptr, fft_inv = nullptr;
+  // grid -> image without w-stacking: complex-to-real inverse of the grid's Hermitian part
+  // (herm_bytes of it at the start of the workspace, the plan's own work buffer after)
+  rocfft_plan fft_c2r = nullptr;
+  size_t herm_bytes = 0, c2r_work_bytes = 0;
   size_t fft_work_bytes = 0;
   int tile = 16;            // tiled gridder tile side
   bool plane_in_key = true; // bin by (tile, plane) rather than tile alone
@@ -255,5 +259,11 @@ hipError_t launch_g2i_correct(const wproj_kernels *k, const void *fgrid, void *i
                               const double *wsum, hipStream_t s);
 hipError_t launch_i2g_precorrect(const wproj_kernels *k, const void *image, void *grid,
                                  hipStream_t s);
+// H = G + conj(G(-k)) on the half spectrum kx in [0, n/2] (twice the Hermitian part of G,
+// whose inverse transform is twice Re IFFT(G)), for the complex-to-real transform.
+hipError_t launch_hermitian_half(const wproj_kernels *k, const void *grid, void *half, hipStream_t s);
+// The correction applied to the real output R of that transform (R = 2 Re IFFT(G)).
+hipError_t launch_g2i_correct_real(const wproj_kernels *k, const void *real, void *image,
+                                   const double *wsum, hipStream_t s);
 
 }  // namespace wproj
