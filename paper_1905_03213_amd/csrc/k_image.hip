@@ -19,9 +19,14 @@ namespace {
 
 // Launch shape of the per-pixel kernels: blockIdx.x * 256 + threadIdx.x is the column,
 // blockIdx.y the row, and blockIdx.z steps through the images (or grids) by gridDim.z;
-// no per-element integer division.
+// no per-element integer division.  The correction kernels take up to kPixZ images per
+// launch row, so that a thread corrects several images' pixels with one kappa lookup
+// (64 images of 1024^2: 0.24 ms with one image per thread, 0.16 ms with a z extent of 16,
+// the same with 4); the Hermitian-half kernel keeps one grid per thread (its transform
+// phase was 0.01-0.03 ms slower with the smaller extents).
 constexpr int kPixThreads = 256;
 constexpr unsigned kMaxGridZ = 65535;
+constexpr unsigned kPixZ = 16;
 
 template <typename Real>
 __global__ void __launch_bounds__(kPixThreads)
@@ -201,8 +206,7 @@ __global__ void __launch_bounds__(kPixThreads)
 }
 
 inline dim3 pixel_grid(int n, int planes) {
-  return dim3((unsigned)((n + kPixThreads - 1) / kPixThreads), (unsigned)n,
-              std::min((unsigned)planes, kMaxGridZ));
+  return dim3((unsigned)((n + kPixThreads - 1) / kPixThreads), (unsigned)n, std::min((unsigned)planes, kPixZ));
 }
 
 }  // namespace
