@@ -85,6 +85,9 @@ def parse():
                     help="only grid the benchmark visibilities --steps times with atomic-slot or "
                          "stable bins (FP32, --tile or 32, chunk 8192): the command the binning "
                          "kernels' traces profile")
+    ap.add_argument("--only", choices=["cfg3", "cfg4", "cfg5"], default=None,
+                    help="only time one of the other workloads (the 4096^2 variable-support one, the "
+                         "64-image batch, or the differentiable model) and print its JSON record")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB device buffer 4 times (a kernel of known traffic "
                          "for scaling hardware byte counters) and exit")
@@ -116,6 +119,11 @@ def main():
         return
     if args.sweep:
         sweep(args, dev)
+        return
+    if args.only:
+        rec = (time_cfg5(dev, args) if args.only == "cfg5" else
+               time_config(args.only, dev, args, measure_lds_peak()["read_add_write"]))
+        print(json.dumps({args.only: rec}), flush=True)
         return
     if args.bin_only:
         wl = synth.cfg2(device=dev, precision="f32", hours=args.hours)
