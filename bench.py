@@ -826,6 +826,11 @@ def time_config(name, dev, args, peak_lds):
     wl = synth.cfg3(device=dev) if name == "cfg3" else synth.cfg4(device=dev)
     prec = "f32_f16table" if name == "cfg3" else "f32"
     params = {**wl.params, "precision": prec, "algorithm": "tiled"}
+    fixed = bool(args.only and args.tile)  # --only with --tile/--chunk: no autotuning
+    if fixed:
+        # the autotuner's binning choice for these rows: aggregated counts for the 64-image
+        # batch (one channel per row, in time order), per-wavefront runs otherwise
+        params.update(tile=args.tile, chunk=args.chunk or 8192, bin_aggregate=name == "cfg4")
     vis = wl.vis.to(torch.complex64)
     wt = wl.weight.to(torch.float32)
     off = wl.image_offsets
@@ -836,7 +841,10 @@ def time_config(name, dev, args, peak_lds):
     n = params["n"]
     img = torch.empty((ni, n, n), dtype=torch.float32, device=dev)
     sw = torch.zeros(ni, dtype=torch.float64, device=dev)
-    tile, chunk = W.autotune(k, wl.uvw, vis, wt, image_offsets=off, workspace=ws)
+    if fixed:
+        tile, chunk = k.tuning()
+    else:
+        tile, chunk = W.autotune(k, wl.uvw, vis, wt, image_offsets=off, workspace=ws)
     # algorithmic LDS bytes: S_p^2 taps x 16 B for every gridded visibility
     fp = W.footprints(k, wl.uvw, wt)
     supp = k.export(W._lib.EXPORT_SUPPORTS).view(torch.int32).to(torch.int64)
